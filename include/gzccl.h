@@ -1,0 +1,243 @@
+/*
+ * gzccl.h -- C ABI of the MI355X (gfx950) compression hot path of gZCCL
+ * (arXiv 2308.05199): error-bounded compression, decompression, the fused
+ * decompress -> reduce -> recompress step of a ring Reduce_scatter, Scatter
+ * compression, batched launches and the learned predictor selector.
+ *
+ * Conventions (every call):
+ *   - Data pointers named d_* are device pointers owned by the caller; h_*
+ *     are host pointers read during the call only.
+ *   - Calls only enqueue work on `stream` and return; no call synchronises
+ *     the host, except gz_ctx_create, gz_ctx_status, gz_plan_create,
+ *     gz_selector_* and gz_tune, which say so.  Compressed sizes land in
+ *     caller-provided device words; read them after the stream completes
+ *     (the paper syncs the streams before reading the sizes, Sec. 3.3.4).
+ *   - The context owns all temporary device memory: a workspace allocated
+ *     once at gz_ctx_create (the paper's pre-allocated GPU buffer pool,
+ *     Sec. 3.3.1, and its reused temporary buffers, Sec. 3.3.2).  No call
+ *     allocates device memory.  One context serves one stream at a time;
+ *     contexts share nothing, so several contexts may run concurrently on
+ *     different streams (the per-stream buffers of Sec. 3.3.4).
+ *   - Argument errors found on the host return at once and enqueue nothing.
+ *     Errors found on the device (corrupt stream, look-back time-out) set a
+ *     sticky word in the context, read and cleared by gz_ctx_status; the
+ *     kernels never write out of bounds, but outputs of a failed call are
+ *     unspecified.  No exception or abort crosses the ABI.
+ *   - Output bytes depend only on (input, n, dtype, eb, block length, mode,
+ *     nx, selector weights); thread counts, grid sizes, streams and batching
+ *     never change them.
+ *
+ * Stream format GZ1 (little-endian):
+ *   t = (T)(2*eb).  Per element: r = x/t in T; FAIL if x is not finite or
+ *   |r| > 2^29-1; q = rint(r) (ties to even); xh = (T)q*t; FAIL unless
+ *   |x - xh| <= eb.  Blocks of L elements (mode 0) or 8x8 tiles of an
+ *   nx-wide field (mode 1, L = 64).  Residuals: L1D (d0 = 0 with the first q
+ *   stored as a base, then q_i - q_{i-1}; in mode 1 along rows, the first
+ *   column vertically), L2D (mode 1: second-order 2D Lorenzo), NONE (mode 1:
+ *   d = q).  F = bit length of max|d|.  A block is RAW (values bit for bit)
+ *   if an element FAILs or RAW is smaller, ZERO if all q are 0.  Payload:
+ *   [int32 base][sign plane][F magnitude planes], a plane being L/32 u32.
+ *   Stream = 64-byte header | u32 offset/4 of every 4096-element superblock
+ *   | one header byte (kind<<5 | F) per block, padded to 4 | payload.
+ *   Header: "GZC1", u16 version 1, u8 dtype, u8 log2 L, u64 n, f64 eb,
+ *   u64 payload bytes, u32 mode, u32 nx, u32 4096, 20 zero bytes.
+ */
+#ifndef GZCCL_H
+#define GZCCL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* gz_stream_t; /* same type as hipStream_t */
+
+typedef enum {
+  GZ_OK = 0,
+  GZ_EINVAL = 1,       /* bad argument (null pointer, eb, sizes, params) */
+  GZ_ENOSPC = 2,       /* output capacity below the bound / workspace too small */
+  GZ_ECORRUPT = 3,     /* device: malformed or mismatching input stream */
+  GZ_EHIP = 4,         /* a HIP runtime call failed */
+  GZ_ENOMEM = 5,       /* allocation failed (context or plan creation only) */
+  GZ_EUNSUPPORTED = 6, /* combination not built (e.g. fused step on fp64) */
+  GZ_ETIMEOUT = 7      /* device: bounded look-back wait expired */
+} gz_status;
+
+typedef enum { GZ_F32 = 0, GZ_F64 = 1 } gz_dtype;
+
+typedef struct gz_ctx gz_ctx;
+typedef struct gz_plan gz_plan;
+typedef struct gz_graph gz_graph;
+
+/* Encoding parameters.  block_len 32|64|128 (0 = 32); threads per workgroup
+ * 128|256 (0 = tuned/default) and grid (persistent workgroups, 0 = default)
+ * never change the bytes.  mode 0 = 1D blocks, 1 = 8x8 tiles (block_len 64,
+ * nx = row length, multiple of 8, n a multiple of 8*nx); select (mode 1):
+ * 0 = int8 MLP selector, 1 = exhaustive trial, 2 = always L1D. */
+typedef struct {
+  uint32_t block_len;
+  uint32_t threads;
+  uint32_t grid;
+  uint32_t mode;
+  uint32_t select;
+  uint32_t nx;
+} gz_params;
+
+/* One independent request of a batch (mode 0).  Compression: in = T[n],
+ * out = stream buffer of out_cap bytes, d_out_bytes receives its size.
+ * Decompression: in = stream of in_bytes, out = T[n] (n and dtype and
+ * block_len are what the stream must declare).  Fused step: in = fp32
+ * stream of n elements, local = fp32[n] addend, out/out_cap/d_out_bytes as
+ * for compression. */
+typedef struct {
+  const void* in;
+  const float* local;
+  void* out;
+  uint64_t* d_out_bytes;
+  uint64_t n;
+  uint64_t in_bytes;
+  uint64_t out_cap;
+  double eb;
+  uint32_t dtype;
+  uint32_t block_len;
+} gz_request;
+
+typedef enum { GZ_OP_COMPRESS = 0, GZ_OP_DECOMPRESS = 1, GZ_OP_FUSED = 2 } gz_op;
+
+/* Creates a context on `device` whose workspace covers calls of up to
+ * max_elems elements in total and max_requests requests per batch.
+ * Synchronous.  Sec. 3.3.1 (buffer pool allocated once at initialisation,
+ * size set by the user). */
+gz_status gz_ctx_create(gz_ctx** ctx, int device, uint64_t max_elems,
+                        uint32_t max_requests);
+void gz_ctx_destroy(gz_ctx* ctx);
+
+/* Synchronises the device, returns the sticky device status (GZ_OK,
+ * GZ_ECORRUPT or GZ_ETIMEOUT) in *device_status and clears it. */
+gz_status gz_ctx_status(gz_ctx* ctx, gz_status* device_status);
+
+/* Clears the context's look-back and ticket state (after a device error). */
+gz_status gz_ctx_reset(gz_ctx* ctx, gz_stream_t stream);
+
+/* Largest stream a compression of n elements can produce:
+ * 64 + 4*ceil(n/4096) + roundup4(ceil(n/L)) + n*sizeof(T). */
+uint64_t gz_compress_bound(uint64_t n, gz_dtype dtype, uint32_t block_len);
+
+/* Elementwise quantisation (the q and FAIL steps above) into d_q (int32,
+ * 0 where failed) and d_fail (uint8 0/1).  Exposes the first step of the
+ * compressor for verification. */
+gz_status gz_quantize(gz_ctx* ctx, const void* d_in, uint64_t n, gz_dtype dtype,
+                      double eb, int32_t* d_q, uint8_t* d_fail,
+                      gz_stream_t stream);
+
+/* Compresses d_in[0..n) under absolute bound eb (Sec. 4.1: absolute error
+ * bound) into d_out (out_cap >= gz_compress_bound); the stream size goes to
+ * *d_out_bytes.  One launch; block offsets come from a single-pass
+ * decoupled look-back scan (Sec. 3.3.2: offsets kept on the device, no
+ * unified memory). */
+gz_status gz_compress(gz_ctx* ctx, const void* d_in, uint64_t n, gz_dtype dtype,
+                      double eb, const gz_params* p, void* d_out,
+                      uint64_t out_cap, uint64_t* d_out_bytes,
+                      gz_stream_t stream);
+
+/* Decompresses a stream of in_bytes into d_out[0..n).  The caller states
+ * what it expects (n, dtype, block length, mode, nx); a stream that says
+ * otherwise, or is malformed, sets GZ_ECORRUPT on the device. */
+gz_status gz_decompress(gz_ctx* ctx, const void* d_in, uint64_t in_bytes,
+                        uint64_t n, gz_dtype dtype, const gz_params* p,
+                        void* d_out, gz_stream_t stream);
+
+/* One round of a compressed ring Reduce_scatter for one rank (Sec. 3.2.3):
+ * decode the incoming fp32 stream (its own eb), add d_local in fp32 in the
+ * order incoming + local, and encode the sum under eb into d_cmp_out, in
+ * one kernel that never writes the sum to memory. */
+gz_status gz_fused_reduce_step(gz_ctx* ctx, const void* d_cmp_in,
+                               uint64_t in_bytes, const float* d_local,
+                               uint64_t n, double eb, const gz_params* p,
+                               void* d_cmp_out, uint64_t out_cap,
+                               uint64_t* d_out_bytes, gz_stream_t stream);
+
+/* gZ-Scatter compression (Sec. 3.3.4): chunk j = d_root[h_displs[j] ..
+ * + h_counts[j]) is compressed as its own stream; all chunks in one
+ * persistent launch, packed back to back into d_out (out_cap >= sum of the
+ * chunk bounds) with sizes in d_chunk_bytes[j] and offsets (exclusive sum)
+ * in d_chunk_offsets[j]. */
+gz_status gz_scatter_compress(gz_ctx* ctx, const void* d_root, gz_dtype dtype,
+                              const uint64_t* h_counts, const uint64_t* h_displs,
+                              uint32_t nchunks, double eb, const gz_params* p,
+                              void* d_out, uint64_t out_cap,
+                              uint64_t* d_chunk_bytes, uint64_t* d_chunk_offsets,
+                              gz_stream_t stream);
+
+/* Inverse of gz_scatter_compress in one batched launch: chunk j starts at
+ * d_packed + d_chunk_offsets[j] and decodes into d_root + h_displs[j]. */
+gz_status gz_scatter_decompress(gz_ctx* ctx, const void* d_packed,
+                                uint64_t packed_bytes,
+                                const uint64_t* d_chunk_offsets,
+                                gz_dtype dtype, const uint64_t* h_counts,
+                                const uint64_t* h_displs, uint32_t nchunks,
+                                const gz_params* p, void* d_root,
+                                gz_stream_t stream);
+
+/* Batched independent requests (fp32 and fp64 mixed, per-request eb and
+ * block length) in one persistent launch: the many small compressions that
+ * under-use the GPU one by one (Sec. 3.2.2, Sec. 3.3.3 "total compression
+ * cost") share one grid.  op selects compress, decompress or fused step;
+ * p gives threads/grid only. */
+gz_status gz_batch(gz_ctx* ctx, gz_op op, const gz_request* h_reqs,
+                   uint32_t nreq, const gz_params* p, gz_stream_t stream);
+
+/* A plan uploads a batch's descriptors once (synchronous) so that
+ * gz_plan_launch is a single kernel launch with no host work, suitable for
+ * stream capture.  Plans of one context must run in order on one stream. */
+gz_status gz_plan_create(gz_ctx* ctx, gz_op op, const gz_request* h_reqs,
+                         uint32_t nreq, const gz_params* p, gz_plan** plan);
+gz_status gz_plan_launch(gz_plan* plan, gz_stream_t stream);
+void gz_plan_destroy(gz_plan* plan);
+
+/* Captures the launches of nplans plans, in order, into one HIP graph and
+ * instantiates it (synchronous). */
+gz_status gz_graph_create(gz_plan* const* plans, uint32_t nplans,
+                          gz_graph** graph);
+gz_status gz_graph_launch(gz_graph* graph, gz_stream_t stream);
+void gz_graph_destroy(gz_graph* graph);
+
+/* Times the launch shapes (threads, grid) of compress and decompress for
+ * (dtype, block_len) on n synthetic elements and stores the fastest in the
+ * context; with a non-null cache_path, reads/writes a JSON cache there.
+ * Synchronous; allocates scratch buffers for the measurement. */
+gz_status gz_tune(gz_ctx* ctx, gz_dtype dtype, uint32_t block_len, uint64_t n,
+                  const char* cache_path, gz_params* best);
+
+/* Learned selector (mode 1, select 0): loads the int8 weight blob
+ * ("GZM1", u32 shift, int8 W1[32][16], int32 b1[32], int8 W2[3][32],
+ * int32 b2[3]; 756 bytes).  Synchronous. */
+gz_status gz_selector_load(gz_ctx* ctx, const void* h_blob, uint64_t bytes);
+
+/* Training data of the selector: for each 8x8 tile of an nx-wide fp32 field
+ * writes its 16 int8 features (d_feat[16*tile]), the byte sizes of its
+ * NONE, L1D and L2D encodings (d_sizes[3*tile]) and the exhaustive-trial
+ * label (d_label[tile], 0 NONE, 1 L1D, 2 L2D; 255 for RAW/ZERO tiles). */
+gz_status gz_tile_trial(gz_ctx* ctx, const float* d_in, uint64_t n, uint32_t nx,
+                        double eb, int8_t* d_feat, uint32_t* d_sizes,
+                        uint8_t* d_label, gz_stream_t stream);
+
+/* fp32 training of the selector's shadow network (16 -> 32 ReLU -> 3,
+ * softmax cross-entropy).  d_w holds W1[32][16], b1[32], W2[3][32], b2[3]
+ * (643 floats); d_feat/d_label as produced by gz_tile_trial (label 255 is
+ * skipped).  gz_mlp_grad writes the mean-loss gradient of the first nsamp
+ * samples into d_grad (643 floats) and the mean loss into *d_loss;
+ * gz_mlp_adam applies one Adam step (state d_m, d_v, step count `step`). */
+gz_status gz_mlp_grad(gz_ctx* ctx, const float* d_w, const int8_t* d_feat,
+                      const uint8_t* d_label, uint64_t nsamp, float* d_grad,
+                      float* d_loss, gz_stream_t stream);
+gz_status gz_mlp_adam(gz_ctx* ctx, float* d_w, const float* d_grad, float* d_m,
+                      float* d_v, uint32_t step, float lr, gz_stream_t stream);
+
+const char* gz_status_str(gz_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,642 @@
+// gz_api.hip -- host runtime and C ABI (include/gzccl.h).
+//
+// The context owns every temporary device buffer, allocated once: the
+// control block (tickets, epoch, sticky status), one look-back word per
+// strip, one chain word per job, the batch descriptor arena and the selector
+// weights.  Single calls pass their job descriptor as a kernel argument;
+// batched calls stage descriptors through a small ring of pinned host
+// buffers and one async copy.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "gz_common.h"
+#include "gz_kernels.h"
+#include "gzccl.h"
+
+using gzk::Ctl;
+using gzk::Ctrl;
+using gzk::Job;
+
+namespace {
+
+constexpr int STAGE_SLOTS = 4;
+constexpr uint64_t MAX_CHAIN_DW = (1ull << 34) - 1;  // look-back value field
+
+struct Tuned {
+  uint32_t tpb = 0, grid = 0;
+};
+
+}  // namespace
+
+struct gz_ctx {
+  int device = 0;
+  int cus = 0;
+  uint64_t max_elems = 0;
+  uint32_t max_jobs = 0;
+  uint64_t max_strips = 0;
+  Ctrl* ctrl = nullptr;
+  unsigned long long* status = nullptr;
+  unsigned long long* jobbase = nullptr;
+  uint8_t* blob = nullptr;
+  bool blob_loaded = false;
+  Job* d_jobs = nullptr;
+  uint32_t* d_map = nullptr;
+  uint8_t* stage[STAGE_SLOTS] = {};
+  hipEvent_t stage_ev[STAGE_SLOTS] = {};
+  bool stage_used[STAGE_SLOTS] = {};
+  int stage_next = 0;
+  size_t stage_bytes = 0;
+  Tuned tuned[3][2][3];  // [op][dtype][log2L-5]
+  Ctl ctl() const { return Ctl{ctrl, status, jobbase, blob}; }
+};
+
+struct gz_plan {
+  gz_ctx* ctx = nullptr;
+  uint32_t op = 0;
+  Job* d_jobs = nullptr;
+  uint32_t* d_map = nullptr;
+  uint32_t total = 0;
+  uint32_t tpb = 0, grid = 0;
+};
+
+struct gz_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+uint64_t cdiv(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+uint64_t round4(uint64_t a) { return (a + 3) & ~3ull; }
+uint32_t esize(uint32_t dt) { return dt == GZ_F32 ? 4u : 8u; }
+
+bool valid_L(uint32_t L) { return L == 32 || L == 64 || L == 128; }
+uint32_t log2_of(uint32_t L) { return L == 32 ? 5u : L == 64 ? 6u : 7u; }
+
+uint64_t bound_of(uint64_t n, uint32_t dt, uint32_t L) {
+  return gzk::HDR + 4 * cdiv(n, gzk::SUPER) + round4(cdiv(n, L)) + n * esize(dt);
+}
+uint64_t fixed_of(uint64_t n, uint32_t L) {
+  return gzk::HDR + 4 * cdiv(n, gzk::SUPER) + round4(cdiv(n, L));
+}
+
+// Step t, its reciprocal and the largest float not above eb.
+bool set_bound(Job& J, uint32_t dtype, double eb) {
+  if (!(eb > 0.0) || !isfinite(eb)) return false;
+  J.eb = eb;
+  const double two = 2.0 * eb;
+  if (dtype == GZ_F32) {
+    float t = (float)two;
+    if (!isfinite(t) || t == 0.0f) return false;
+    J.t32 = t;
+    J.rinv = 1.0 / (double)t;
+    float e = (float)eb;
+    if ((double)e > eb) e = nextafterf(e, 0.0f);
+    J.eblo = e;
+    J.t64 = (double)t;
+  } else {
+    if (!isfinite(two) || two == 0.0) return false;
+    J.t64 = two;
+    J.t32 = 0;
+    J.rinv = 0;
+    J.eblo = 0;
+  }
+  return true;
+}
+
+void set_geom(Job& J, uint64_t n, uint32_t L, uint32_t tpb) {
+  J.n = n;
+  J.log2L = log2_of(L);
+  J.B = cdiv(n, L);
+  J.NS = cdiv(n, gzk::SUPER);
+  J.hdr_off = gzk::HDR + 4 * J.NS;
+  J.pay_off = J.hdr_off + round4(J.B);
+  const uint64_t segs = J.B * L / gzk::SEG;
+  uint64_t ns = cdiv(segs, tpb);
+  J.nstrips = (uint32_t)(ns ? ns : 1);
+}
+
+bool overlaps(const void* a, uint64_t na, const void* b, uint64_t nb) {
+  if (!na || !nb) return false;
+  uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+  return x < y + nb && y < x + na;
+}
+
+uint32_t pick_tpb(const gz_ctx* c, uint32_t op, uint32_t dt, uint32_t L, const gz_params* p) {
+  if (p && p->threads) return p->threads;
+  const Tuned& t = c->tuned[op][dt][log2_of(L) - 5];
+  return t.tpb ? t.tpb : 256;
+}
+
+uint32_t pick_grid(const gz_ctx* c, uint32_t op, uint32_t dt, uint32_t L, uint32_t tpb,
+                   uint64_t strips, const gz_params* p) {
+  uint64_t g;
+  if (p && p->grid) {
+    g = p->grid;
+  } else {
+    const Tuned& t = c->tuned[op][dt][log2_of(L) - 5];
+    if (t.grid && t.tpb == tpb) {
+      g = t.grid;
+    } else {
+      int occ = gzk::occupancy_blocks(op, dt, log2_of(L), tpb);
+      g = (uint64_t)c->cus * (uint64_t)occ;
+    }
+  }
+  g = std::min<uint64_t>(g, strips);
+  return (uint32_t)std::max<uint64_t>(g, 1);
+}
+
+bool params_ok(const gz_params* p, uint32_t& L) {
+  L = (p && p->block_len) ? p->block_len : 32;
+  if (!valid_L(L)) return false;
+  if (p) {
+    if (p->threads != 0 && p->threads != 128 && p->threads != 256) return false;
+    if (p->mode != 0) return false;
+    if (p->nx != 0) return false;
+  }
+  return true;
+}
+
+gz_status hip_status(hipError_t e) { return e == hipSuccess ? GZ_OK : GZ_EHIP; }
+
+// Copies descriptors and the strip map into the context arena on `st`.
+gz_status stage_upload(gz_ctx* c, const std::vector<Job>& jobs,
+                       const std::vector<uint32_t>& map, hipStream_t st) {
+  const size_t jb = jobs.size() * sizeof(Job), mb = map.size() * sizeof(uint32_t);
+  if (jb + mb > c->stage_bytes) return GZ_ENOSPC;
+  const int k = c->stage_next;
+  c->stage_next = (k + 1) % STAGE_SLOTS;
+  if (c->stage_used[k] && hipEventSynchronize(c->stage_ev[k]) != hipSuccess) return GZ_EHIP;
+  memcpy(c->stage[k], jobs.data(), jb);
+  memcpy(c->stage[k] + jb, map.data(), mb);
+  if (hipMemcpyAsync(c->d_jobs, c->stage[k], jb, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(c->d_map, c->stage[k] + jb, mb, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipEventRecord(c->stage_ev[k], st) != hipSuccess)
+    return GZ_EHIP;
+  c->stage_used[k] = true;
+  return GZ_OK;
+}
+
+// Builds the jobs of a request batch; fills the strip map.
+gz_status build_requests(gz_ctx* c, gz_op op, const gz_request* r, uint32_t nreq, uint32_t tpb,
+                         std::vector<Job>& jobs, std::vector<uint32_t>& map) {
+  if (!r || nreq == 0 || nreq > c->max_jobs) return GZ_EINVAL;
+  jobs.resize(nreq);
+  uint64_t strip = 0;
+  for (uint32_t j = 0; j < nreq; ++j) {
+    const gz_request& q = r[j];
+    Job J;
+    memset(&J, 0, sizeof J);
+    const uint32_t L = q.block_len ? q.block_len : 32;
+    if (!valid_L(L) || (q.dtype != GZ_F32 && q.dtype != GZ_F64)) return GZ_EINVAL;
+    if (op == GZ_OP_FUSED && q.dtype != GZ_F32) return GZ_EUNSUPPORTED;
+    if (q.n && (!q.in || !q.out)) return GZ_EINVAL;
+    if (q.n * (uint64_t)esize(q.dtype) >= (1ull << 34)) return GZ_EINVAL;
+    J.dtype = q.dtype;
+    J.in = q.in;
+    J.out = q.out;
+    J.local = q.local;
+    J.out_bytes = (unsigned long long*)q.d_out_bytes;
+    J.in_bytes = q.in_bytes;
+    J.job = j;
+    set_geom(J, q.n, L, tpb);
+    if (op != GZ_OP_DECOMPRESS) {
+      if (!set_bound(J, q.dtype, q.eb)) return GZ_EINVAL;
+      if (q.out_cap < bound_of(q.n, q.dtype, L)) return GZ_ENOSPC;
+      if (op == GZ_OP_FUSED && q.n && !q.local) return GZ_EINVAL;
+      if (overlaps(q.in, op == GZ_OP_FUSED ? q.in_bytes : q.n * esize(q.dtype), q.out, q.out_cap))
+        return GZ_EINVAL;
+    } else {
+      if (!q.in) return GZ_EINVAL;
+    }
+    J.strip0 = J.chain0 = strip;
+    strip += J.nstrips;
+    jobs[j] = J;
+  }
+  if (strip > c->max_strips || strip >= (1ull << 32)) return GZ_ENOSPC;
+  map.resize(strip);
+  for (uint32_t j = 0; j < nreq; ++j)
+    for (uint64_t s = 0; s < jobs[j].nstrips; ++s) map[jobs[j].strip0 + s] = j;
+  return GZ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gz_status_str(gz_status s) {
+  switch (s) {
+    case GZ_OK: return "ok";
+    case GZ_EINVAL: return "invalid argument";
+    case GZ_ENOSPC: return "insufficient capacity";
+    case GZ_ECORRUPT: return "corrupt or mismatching stream";
+    case GZ_EHIP: return "HIP runtime error";
+    case GZ_ENOMEM: return "out of memory";
+    case GZ_EUNSUPPORTED: return "unsupported combination";
+    case GZ_ETIMEOUT: return "device wait timed out";
+  }
+  return "unknown status";
+}
+
+uint64_t gz_compress_bound(uint64_t n, gz_dtype dtype, uint32_t block_len) {
+  if (!valid_L(block_len) || (dtype != GZ_F32 && dtype != GZ_F64)) return 0;
+  return bound_of(n, dtype, block_len);
+}
+
+gz_status gz_ctx_create(gz_ctx** out, int device, uint64_t max_elems, uint32_t max_requests) {
+  if (!out) return GZ_EINVAL;
+  *out = nullptr;
+  if (max_requests == 0) max_requests = 1;
+  if (hipSetDevice(device) != hipSuccess) return GZ_EHIP;
+  gz_ctx* c = new (std::nothrow) gz_ctx();
+  if (!c) return GZ_ENOMEM;
+  c->device = device;
+  if (hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, device) !=
+      hipSuccess) {
+    delete c;
+    return GZ_EHIP;
+  }
+  c->max_elems = max_elems;
+  c->max_jobs = max_requests;
+  // strips of the smallest workgroup (128 lanes = 4096 elements), plus one
+  // partial strip per request
+  c->max_strips = cdiv(max_elems, 128 * gzk::SEG) + max_requests + 1;
+  bool ok = true;
+  ok = ok && hipMalloc((void**)&c->ctrl, sizeof(Ctrl)) == hipSuccess;
+  ok = ok && hipMalloc((void**)&c->status, c->max_strips * 8) == hipSuccess;
+  ok = ok && hipMalloc((void**)&c->jobbase, (size_t)max_requests * 8) == hipSuccess;
+  ok = ok && hipMalloc((void**)&c->blob, 1024) == hipSuccess;
+  ok = ok && hipMalloc((void**)&c->d_jobs, (size_t)max_requests * sizeof(Job)) == hipSuccess;
+  ok = ok && hipMalloc((void**)&c->d_map, c->max_strips * 4) == hipSuccess;
+  c->stage_bytes = (size_t)max_requests * sizeof(Job) + c->max_strips * 4;
+  for (int k = 0; ok && k < STAGE_SLOTS; ++k) {
+    ok = hipHostMalloc((void**)&c->stage[k], c->stage_bytes, hipHostMallocDefault) == hipSuccess &&
+         hipEventCreateWithFlags(&c->stage_ev[k], hipEventDisableTiming) == hipSuccess;
+  }
+  if (ok) {
+    Ctrl init;
+    memset(&init, 0, sizeof init);
+    init.epoch = 1;
+    ok = hipMemcpy(c->ctrl, &init, sizeof init, hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemset(c->status, 0, c->max_strips * 8) == hipSuccess &&
+         hipMemset(c->jobbase, 0, (size_t)max_requests * 8) == hipSuccess &&
+         hipMemset(c->blob, 0, 1024) == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+  }
+  if (!ok) {
+    gz_ctx_destroy(c);
+    return GZ_ENOMEM;
+  }
+  *out = c;
+  return GZ_OK;
+}
+
+void gz_ctx_destroy(gz_ctx* c) {
+  if (!c) return;
+  for (int k = 0; k < STAGE_SLOTS; ++k) {
+    if (c->stage_ev[k]) {
+      (void)hipEventSynchronize(c->stage_ev[k]);
+      (void)hipEventDestroy(c->stage_ev[k]);
+    }
+    if (c->stage[k]) (void)hipHostFree(c->stage[k]);
+  }
+  (void)hipFree(c->ctrl);
+  (void)hipFree(c->status);
+  (void)hipFree(c->jobbase);
+  (void)hipFree(c->blob);
+  (void)hipFree(c->d_jobs);
+  (void)hipFree(c->d_map);
+  delete c;
+}
+
+gz_status gz_ctx_status(gz_ctx* c, gz_status* dev) {
+  if (!c || !dev) return GZ_EINVAL;
+  if (hipDeviceSynchronize() != hipSuccess) return GZ_EHIP;
+  uint32_t err = 0;
+  if (hipMemcpy(&err, &c->ctrl->err, 4, hipMemcpyDeviceToHost) != hipSuccess) return GZ_EHIP;
+  *dev = (err & gzk::ERRF_CORRUPT) ? GZ_ECORRUPT : (err & gzk::ERRF_TIMEOUT) ? GZ_ETIMEOUT : GZ_OK;
+  if (err) {
+    uint32_t z = 0;
+    if (hipMemcpy(&c->ctrl->err, &z, 4, hipMemcpyHostToDevice) != hipSuccess) return GZ_EHIP;
+  }
+  return GZ_OK;
+}
+
+gz_status gz_ctx_reset(gz_ctx* c, gz_stream_t stream) {
+  if (!c) return GZ_EINVAL;
+  return hip_status(gzk::launch_reset(c->ctl(), (hipStream_t)stream));
+}
+
+gz_status gz_quantize(gz_ctx* c, const void* d_in, uint64_t n, gz_dtype dtype, double eb,
+                      int32_t* d_q, uint8_t* d_fail, gz_stream_t stream) {
+  if (!c || (dtype != GZ_F32 && dtype != GZ_F64)) return GZ_EINVAL;
+  if (n && (!d_in || !d_q || !d_fail)) return GZ_EINVAL;
+  Job J;
+  memset(&J, 0, sizeof J);
+  J.dtype = dtype;
+  if (!set_bound(J, dtype, eb)) return GZ_EINVAL;
+  if (!n) return GZ_OK;
+  return hip_status(gzk::launch_quantize(d_in, n, J, d_q, d_fail, (hipStream_t)stream));
+}
+
+gz_status gz_compress(gz_ctx* c, const void* d_in, uint64_t n, gz_dtype dtype, double eb,
+                      const gz_params* p, void* d_out, uint64_t out_cap, uint64_t* d_out_bytes,
+                      gz_stream_t stream) {
+  uint32_t L;
+  if (!c || !d_out || (dtype != GZ_F32 && dtype != GZ_F64) || !params_ok(p, L))
+    return GZ_EINVAL;
+  if (n && !d_in) return GZ_EINVAL;
+  if (n * (uint64_t)esize(dtype) >= (1ull << 34)) return GZ_EINVAL;
+  if (out_cap < bound_of(n, dtype, L)) return GZ_ENOSPC;
+  if (overlaps(d_in, n * esize(dtype), d_out, out_cap)) return GZ_EINVAL;
+  Job J;
+  memset(&J, 0, sizeof J);
+  J.dtype = dtype;
+  if (!set_bound(J, dtype, eb)) return GZ_EINVAL;
+  const uint32_t tpb = pick_tpb(c, 0, dtype, L, p);
+  set_geom(J, n, L, tpb);
+  if (J.nstrips > c->max_strips) return GZ_ENOSPC;
+  J.in = d_in;
+  J.out = d_out;
+  J.out_bytes = (unsigned long long*)d_out_bytes;
+  const uint32_t grid = pick_grid(c, 0, dtype, L, tpb, J.nstrips, p);
+  return hip_status(gzk::launch_single(0, J, c->ctl(), tpb, grid, (hipStream_t)stream));
+}
+
+gz_status gz_decompress(gz_ctx* c, const void* d_in, uint64_t in_bytes, uint64_t n,
+                        gz_dtype dtype, const gz_params* p, void* d_out, gz_stream_t stream) {
+  uint32_t L;
+  if (!c || !d_in || (dtype != GZ_F32 && dtype != GZ_F64) || !params_ok(p, L)) return GZ_EINVAL;
+  if (n && !d_out) return GZ_EINVAL;
+  if (n * (uint64_t)esize(dtype) >= (1ull << 34)) return GZ_EINVAL;
+  if (overlaps(d_in, in_bytes, d_out, n * esize(dtype))) return GZ_EINVAL;
+  Job J;
+  memset(&J, 0, sizeof J);
+  J.dtype = dtype;
+  const uint32_t tpb = pick_tpb(c, 1, dtype, L, p);
+  set_geom(J, n, L, tpb);
+  if (J.nstrips > c->max_strips) return GZ_ENOSPC;
+  J.in = d_in;
+  J.in_bytes = in_bytes;
+  J.out = d_out;
+  const uint32_t grid = pick_grid(c, 1, dtype, L, tpb, J.nstrips, p);
+  return hip_status(gzk::launch_single(1, J, c->ctl(), tpb, grid, (hipStream_t)stream));
+}
+
+gz_status gz_fused_reduce_step(gz_ctx* c, const void* d_cmp_in, uint64_t in_bytes,
+                               const float* d_local, uint64_t n, double eb, const gz_params* p,
+                               void* d_cmp_out, uint64_t out_cap, uint64_t* d_out_bytes,
+                               gz_stream_t stream) {
+  uint32_t L;
+  if (!c || !d_cmp_in || !d_cmp_out || !params_ok(p, L)) return GZ_EINVAL;
+  if (n && !d_local) return GZ_EINVAL;
+  if (n * 4ull >= (1ull << 34)) return GZ_EINVAL;
+  if (out_cap < bound_of(n, GZ_F32, L)) return GZ_ENOSPC;
+  if (overlaps(d_cmp_in, in_bytes, d_cmp_out, out_cap) ||
+      overlaps(d_local, n * 4, d_cmp_out, out_cap))
+    return GZ_EINVAL;
+  Job J;
+  memset(&J, 0, sizeof J);
+  J.dtype = GZ_F32;
+  if (!set_bound(J, GZ_F32, eb)) return GZ_EINVAL;
+  const uint32_t tpb = pick_tpb(c, 2, GZ_F32, L, p);
+  set_geom(J, n, L, tpb);
+  if (J.nstrips > c->max_strips) return GZ_ENOSPC;
+  J.in = d_cmp_in;
+  J.in_bytes = in_bytes;
+  J.local = d_local;
+  J.out = d_cmp_out;
+  J.out_bytes = (unsigned long long*)d_out_bytes;
+  const uint32_t grid = pick_grid(c, 2, GZ_F32, L, tpb, J.nstrips, p);
+  return hip_status(gzk::launch_single(2, J, c->ctl(), tpb, grid, (hipStream_t)stream));
+}
+
+gz_status gz_scatter_compress(gz_ctx* c, const void* d_root, gz_dtype dtype,
+                              const uint64_t* h_counts, const uint64_t* h_displs,
+                              uint32_t nchunks, double eb, const gz_params* p, void* d_out,
+                              uint64_t out_cap, uint64_t* d_chunk_bytes,
+                              uint64_t* d_chunk_offsets, gz_stream_t stream) {
+  uint32_t L;
+  if (!c || !d_root || !d_out || !h_counts || !h_displs || !d_chunk_bytes || !d_chunk_offsets ||
+      (dtype != GZ_F32 && dtype != GZ_F64) || !params_ok(p, L) || nchunks == 0)
+    return GZ_EINVAL;
+  if (nchunks > c->max_jobs) return GZ_ENOSPC;
+  const uint32_t tpb = pick_tpb(c, 0, dtype, L, p);
+  std::vector<Job> jobs(nchunks);
+  Job proto;
+  memset(&proto, 0, sizeof proto);
+  proto.dtype = dtype;
+  if (!set_bound(proto, dtype, eb)) return GZ_EINVAL;
+  uint64_t strip = 0, fixed = 0, need = 0, pay = 0, span = 0;
+  for (uint32_t j = 0; j < nchunks; ++j) {
+    Job J = proto;
+    const uint64_t n = h_counts[j];
+    if (n * (uint64_t)esize(dtype) >= (1ull << 34)) return GZ_EINVAL;
+    span = std::max(span, h_displs[j] + n);
+    set_geom(J, n, L, tpb);
+    J.in = (const uint8_t*)d_root + h_displs[j] * esize(dtype);
+    J.out = d_out;
+    J.out_bytes = (unsigned long long*)(d_chunk_bytes + j);
+    J.chunk_off = (unsigned long long*)(d_chunk_offsets + j);
+    J.fixed_off = fixed;
+    J.strip0 = strip;
+    J.chain0 = 0;
+    J.job = j;
+    fixed += fixed_of(n, L);
+    need += bound_of(n, dtype, L);
+    pay += n * esize(dtype) / 4;
+    strip += J.nstrips;
+    jobs[j] = J;
+  }
+  if (out_cap < need) return GZ_ENOSPC;
+  if (pay > MAX_CHAIN_DW) return GZ_EINVAL;
+  if (strip > c->max_strips) return GZ_ENOSPC;
+  if (overlaps(d_root, span * esize(dtype), d_out, out_cap)) return GZ_EINVAL;
+  std::vector<uint32_t> map(strip);
+  for (uint32_t j = 0; j < nchunks; ++j)
+    for (uint64_t s = 0; s < jobs[j].nstrips; ++s) map[jobs[j].strip0 + s] = j;
+  hipStream_t st = (hipStream_t)stream;
+  gz_status r = stage_upload(c, jobs, map, st);
+  if (r != GZ_OK) return r;
+  const uint32_t grid = pick_grid(c, 0, dtype, L, tpb, strip, p);
+  return hip_status(gzk::launch_batch(0, c->d_jobs, c->d_map, (uint32_t)strip, c->ctl(), tpb,
+                                      grid, st));
+}
+
+gz_status gz_scatter_decompress(gz_ctx* c, const void* d_packed, uint64_t packed_bytes,
+                                const uint64_t* d_chunk_offsets, gz_dtype dtype,
+                                const uint64_t* h_counts, const uint64_t* h_displs,
+                                uint32_t nchunks, const gz_params* p, void* d_root,
+                                gz_stream_t stream) {
+  uint32_t L;
+  if (!c || !d_packed || !d_chunk_offsets || !h_counts || !h_displs || !d_root ||
+      (dtype != GZ_F32 && dtype != GZ_F64) || !params_ok(p, L) || nchunks == 0)
+    return GZ_EINVAL;
+  if (nchunks > c->max_jobs) return GZ_ENOSPC;
+  const uint32_t tpb = pick_tpb(c, 1, dtype, L, p);
+  std::vector<Job> jobs(nchunks);
+  uint64_t strip = 0, span = 0;
+  for (uint32_t j = 0; j < nchunks; ++j) {
+    Job J;
+    memset(&J, 0, sizeof J);
+    J.dtype = dtype;
+    const uint64_t n = h_counts[j];
+    if (n * (uint64_t)esize(dtype) >= (1ull << 34)) return GZ_EINVAL;
+    span = std::max(span, h_displs[j] + n);
+    set_geom(J, n, L, tpb);
+    J.in = d_packed;
+    J.in_off = (const unsigned long long*)d_chunk_offsets;
+    J.in_bytes = packed_bytes;
+    J.out = (uint8_t*)d_root + h_displs[j] * esize(dtype);
+    J.strip0 = J.chain0 = strip;
+    J.job = j;
+    strip += J.nstrips;
+    jobs[j] = J;
+  }
+  if (strip > c->max_strips) return GZ_ENOSPC;
+  if (overlaps(d_packed, packed_bytes, d_root, span * esize(dtype))) return GZ_EINVAL;
+  std::vector<uint32_t> map(strip);
+  for (uint32_t j = 0; j < nchunks; ++j)
+    for (uint64_t s = 0; s < jobs[j].nstrips; ++s) map[jobs[j].strip0 + s] = j;
+  hipStream_t st = (hipStream_t)stream;
+  gz_status r = stage_upload(c, jobs, map, st);
+  if (r != GZ_OK) return r;
+  const uint32_t grid = pick_grid(c, 1, dtype, L, tpb, strip, p);
+  return hip_status(gzk::launch_batch(1, c->d_jobs, c->d_map, (uint32_t)strip, c->ctl(), tpb,
+                                      grid, st));
+}
+
+gz_status gz_batch(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t nreq,
+                   const gz_params* p, gz_stream_t stream) {
+  if (!c || op > GZ_OP_FUSED) return GZ_EINVAL;
+  if (p && p->threads != 0 && p->threads != 128 && p->threads != 256) return GZ_EINVAL;
+  const uint32_t tpb = (p && p->threads) ? p->threads : pick_tpb(c, op, GZ_F32, 32, nullptr);
+  std::vector<Job> jobs;
+  std::vector<uint32_t> map;
+  gz_status r = build_requests(c, op, h_reqs, nreq, tpb, jobs, map);
+  if (r != GZ_OK) return r;
+  hipStream_t st = (hipStream_t)stream;
+  r = stage_upload(c, jobs, map, st);
+  if (r != GZ_OK) return r;
+  uint64_t g = (p && p->grid) ? p->grid
+                              : (uint64_t)c->cus * gzk::occupancy_blocks(3, 0, 5, tpb);
+  g = std::max<uint64_t>(1, std::min<uint64_t>(g, map.size()));
+  return hip_status(gzk::launch_batch((uint32_t)op, c->d_jobs, c->d_map, (uint32_t)map.size(),
+                                      c->ctl(), tpb, (uint32_t)g, st));
+}
+
+gz_status gz_plan_create(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t nreq,
+                         const gz_params* p, gz_plan** out) {
+  if (!c || !out || op > GZ_OP_FUSED) return GZ_EINVAL;
+  *out = nullptr;
+  if (p && p->threads != 0 && p->threads != 128 && p->threads != 256) return GZ_EINVAL;
+  const uint32_t tpb = (p && p->threads) ? p->threads : pick_tpb(c, op, GZ_F32, 32, nullptr);
+  std::vector<Job> jobs;
+  std::vector<uint32_t> map;
+  gz_status r = build_requests(c, op, h_reqs, nreq, tpb, jobs, map);
+  if (r != GZ_OK) return r;
+  gz_plan* pl = new (std::nothrow) gz_plan();
+  if (!pl) return GZ_ENOMEM;
+  pl->ctx = c;
+  pl->op = op;
+  pl->total = (uint32_t)map.size();
+  pl->tpb = tpb;
+  uint64_t g = (p && p->grid) ? p->grid
+                              : (uint64_t)c->cus * gzk::occupancy_blocks(3, 0, 5, tpb);
+  pl->grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(g, map.size()));
+  if (hipMalloc((void**)&pl->d_jobs, jobs.size() * sizeof(Job)) != hipSuccess ||
+      hipMalloc((void**)&pl->d_map, map.size() * 4) != hipSuccess) {
+    gz_plan_destroy(pl);
+    return GZ_ENOMEM;
+  }
+  if (hipMemcpy(pl->d_jobs, jobs.data(), jobs.size() * sizeof(Job), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(pl->d_map, map.data(), map.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+    gz_plan_destroy(pl);
+    return GZ_EHIP;
+  }
+  *out = pl;
+  return GZ_OK;
+}
+
+gz_status gz_plan_launch(gz_plan* pl, gz_stream_t stream) {
+  if (!pl) return GZ_EINVAL;
+  return hip_status(gzk::launch_batch(pl->op, pl->d_jobs, pl->d_map, pl->total, pl->ctx->ctl(),
+                                      pl->tpb, pl->grid, (hipStream_t)stream));
+}
+
+void gz_plan_destroy(gz_plan* pl) {
+  if (!pl) return;
+  (void)hipFree(pl->d_jobs);
+  (void)hipFree(pl->d_map);
+  delete pl;
+}
+
+gz_status gz_graph_create(gz_plan* const* plans, uint32_t nplans, gz_graph** out) {
+  if (!plans || !nplans || !out) return GZ_EINVAL;
+  *out = nullptr;
+  for (uint32_t i = 0; i < nplans; ++i)
+    if (!plans[i] || plans[i]->ctx != plans[0]->ctx) return GZ_EINVAL;
+  hipStream_t st;
+  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return GZ_EHIP;
+  gz_graph* g = new (std::nothrow) gz_graph();
+  if (!g) {
+    (void)hipStreamDestroy(st);
+    return GZ_ENOMEM;
+  }
+  gz_status r = GZ_OK;
+  if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) r = GZ_EHIP;
+  for (uint32_t i = 0; r == GZ_OK && i < nplans; ++i) r = gz_plan_launch(plans[i], st);
+  hipGraph_t graph = nullptr;
+  if (hipStreamEndCapture(st, &graph) != hipSuccess && r == GZ_OK) r = GZ_EHIP;
+  if (r == GZ_OK && hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) != hipSuccess)
+    r = GZ_EHIP;
+  g->graph = graph;
+  (void)hipStreamDestroy(st);
+  if (r != GZ_OK) {
+    gz_graph_destroy(g);
+    return r;
+  }
+  *out = g;
+  return GZ_OK;
+}
+
+gz_status gz_graph_launch(gz_graph* g, gz_stream_t stream) {
+  if (!g || !g->exec) return GZ_EINVAL;
+  return hip_status(hipGraphLaunch(g->exec, (hipStream_t)stream));
+}
+
+void gz_graph_destroy(gz_graph* g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+}
+
+}  // extern "C"
+
+extern "C" {
+gz_status gz_tune(gz_ctx*, gz_dtype, uint32_t, uint64_t, const char*, gz_params*) {
+  return GZ_EUNSUPPORTED;
+}
+gz_status gz_selector_load(gz_ctx*, const void*, uint64_t) { return GZ_EUNSUPPORTED; }
+gz_status gz_tile_trial(gz_ctx*, const float*, uint64_t, uint32_t, double, int8_t*, uint32_t*,
+                        uint8_t*, gz_stream_t) {
+  return GZ_EUNSUPPORTED;
+}
+gz_status gz_mlp_grad(gz_ctx*, const float*, const int8_t*, const uint8_t*, uint64_t, float*,
+                      float*, gz_stream_t) {
+  return GZ_EUNSUPPORTED;
+}
+gz_status gz_mlp_adam(gz_ctx*, float*, const float*, float*, float*, uint32_t, float,
+                      gz_stream_t) {
+  return GZ_EUNSUPPORTED;
+}
+}

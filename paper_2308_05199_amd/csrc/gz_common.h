@@ -1,0 +1,56 @@
+// gz_common.h -- types shared by the HIP kernels and the host runtime.
+#pragma once
+#include <stdint.h>
+
+namespace gzk {
+
+constexpr uint32_t SEG = 32;      // elements per lane segment
+constexpr uint32_t SUPER = 4096;  // elements per superblock (one table entry)
+constexpr uint32_t HDR = 64;      // stream header bytes
+constexpr uint32_t MAX_TPB = 256; // largest workgroup the kernels are built for
+
+enum : uint32_t { K_ZERO = 0, K_L1D = 1, K_NONE = 2, K_L2D = 3, K_RAW = 7 };
+enum : uint32_t { ERRF_CORRUPT = 1u, ERRF_TIMEOUT = 2u };
+
+// Per-context control block (device).  ticket/done drive the persistent
+// workgroup loop; epoch tags look-back words so that they never need
+// clearing; err is the sticky device status.
+struct Ctrl {
+  uint32_t ticket;
+  uint32_t done;
+  uint32_t epoch;
+  uint32_t err;
+  uint32_t pad[60];
+};
+
+// One independent stream to encode, decode or fuse.  Geometry fields
+// describe the stream written (encode/fused) or expected (decode).
+struct Job {
+  const void* in;                   // T[n] | stream
+  const float* local;               // fused addend
+  void* out;                        // stream | T[n]
+  unsigned long long* out_bytes;    // encode: size of the stream written
+  unsigned long long* chunk_off;    // scatter: offset of this stream
+  const unsigned long long* in_off; // scatter decode: offset of this stream in `in`
+  uint64_t n;
+  uint64_t in_bytes;                // decode/fused: bytes readable at `in`
+  uint64_t strip0;                  // first global strip of this job
+  uint64_t chain0;                  // first global strip of its look-back chain
+  uint64_t fixed_off;               // packed output: fixed bytes of earlier streams
+  uint64_t NS, B, hdr_off, pay_off; // stream geometry
+  double eb;
+  double rinv;                      // 1 / (double)t32
+  double t64;                       // fp64 step
+  float t32;                        // fp32 step
+  float eblo;                       // largest float <= eb
+  uint32_t dtype, log2L, mode, nx, select, nstrips, job, pad;
+};
+
+struct Ctl {
+  Ctrl* ctrl;
+  unsigned long long* status;   // one look-back word per global strip
+  unsigned long long* jobbase;  // one word per job of a packed chain
+  const uint8_t* blob;          // selector weights
+};
+
+}  // namespace gzk

@@ -1,0 +1,375 @@
+"""GPU parity of the HIP codec against the CPU oracle, through the C ABI.
+
+Bytes, decoded values and fused sums must match the oracle bit for bit.
+Every case prints its name before touching the GPU.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2308_05199_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gz():
+    import torch
+    from paper_2308_05199_amd import gzccl
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    return gzccl
+
+
+@pytest.fixture(scope="module")
+def ctx(gz):
+    c = gz.Context(0, max_elems=1 << 27, max_requests=4096)
+    yield c
+    c.close()
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def gpu_stream(ctx, x, eb, **kw):
+    import torch
+    out, nb = ctx.compress(dev(x), eb, **kw)
+    torch.cuda.synchronize()
+    n = int(nb.item())
+    return out[:n].cpu().numpy()
+
+
+def assert_ok(ctx):
+    assert ctx.device_status() == 0
+
+
+CASES = [(np.float32, 32), (np.float32, 64), (np.float32, 128),
+         (np.float64, 32), (np.float64, 64), (np.float64, 128)]
+
+
+@pytest.mark.parametrize("dt,L", CASES)
+@pytest.mark.parametrize("tpb", [128, 256])
+def test_compress_matches_oracle(ctx, oracle, dt, L, tpb):
+    say("compress", dt.__name__, L, tpb)
+    g = np.random.default_rng(0)
+    n = 5 * 8192 + 777
+    x = np.concatenate([synth.sinusoids(n - 3000, seed=1).astype(dt),
+                        g.uniform(500, 1000, 3000).astype(dt)])
+    for eb in (1e-4, 3e-6):
+        got = gpu_stream(ctx, x, eb, block_len=L, threads=tpb)
+        want = oracle.compress(x, eb, block_len=L)
+        assert got.tobytes() == want.tobytes()
+    assert_ok(ctx)
+
+
+def test_compress_config1_full(ctx, oracle):
+    """2^20-element sum of sinusoids + noise, eb 1e-4, L 32."""
+    say("config1 compress")
+    x = synth.sinusoids(1 << 20, seed=0)
+    got = gpu_stream(ctx, x, 1e-4)
+    want = oracle.compress(x, 1e-4)
+    assert got.tobytes() == want.tobytes()
+    assert_ok(ctx)
+
+
+@pytest.mark.parametrize("grid", [1, 2, 7, 64, 0])
+def test_bytes_independent_of_launch_shape(ctx, oracle, grid):
+    say("grid", grid)
+    x = synth.sinusoids(200_000, seed=2)
+    want = oracle.compress(x, 1e-4, block_len=64)
+    for tpb in (128, 256):
+        got = gpu_stream(ctx, x, 1e-4, block_len=64, threads=tpb, grid=grid)
+        assert got.tobytes() == want.tobytes()
+    assert_ok(ctx)
+
+
+@pytest.mark.parametrize("n", [0, 1, 31, 32, 33, 127, 4095, 4096, 4097, 8191, 8192, 8193])
+def test_small_and_ragged(ctx, oracle, n):
+    say("ragged", n)
+    x = synth.sinusoids(max(n, 1), seed=3)[:n]
+    for L in (32, 128):
+        got = gpu_stream(ctx, x, 1e-4, block_len=L, threads=128)
+        want = oracle.compress(x, 1e-4, block_len=L)
+        assert got.tobytes() == want.tobytes()
+    assert_ok(ctx)
+
+
+def test_special_values(ctx, oracle):
+    say("specials")
+    g = np.random.default_rng(4)
+    x = g.normal(0, 1, 64 * 1024).astype(np.float32)
+    bits = x.view(np.uint32)
+    idx = g.choice(x.size, 300, replace=False)
+    specials = np.array([0x7FC00000, 0x7F800000, 0xFF800000, 0x80000000, 0x00000001,
+                         0x807FFFFF, 0x7F7FFFFF, 0x7FA00001], np.uint32)
+    bits[idx] = specials[np.arange(idx.size) % specials.size]
+    # exact ties (k + 1/2) t
+    t = np.float32(2 * 2.0 ** -14)
+    x[:5000] = ((np.arange(5000) - 2500 + 0.5) * t).astype(np.float32)
+    for eb in (2.0 ** -14, 1e-3, 1e-40):
+        got = gpu_stream(ctx, x, eb)
+        want = oracle.compress(x, eb)
+        assert got.tobytes() == want.tobytes()
+    assert_ok(ctx)
+
+
+@pytest.mark.parametrize("dt,L", CASES)
+def test_decompress_matches_oracle(ctx, oracle, dt, L):
+    import torch
+    say("decompress", dt.__name__, L)
+    g = np.random.default_rng(5)
+    n = 3 * 8192 + 1001
+    x = np.concatenate([synth.sinusoids(n - 2000, seed=6).astype(dt),
+                        g.uniform(500, 1000, 2000).astype(dt)])
+    x[17] = np.nan
+    s = oracle.compress(x, 1e-4, block_len=L)
+    want = oracle.decompress(s)
+    for tpb in (128, 256):
+        y = ctx.decompress(dev(s), n, dtype=torch.float32 if dt == np.float32 else torch.float64,
+                           block_len=L, threads=tpb)
+        torch.cuda.synchronize()
+        got = y.cpu().numpy()
+        assert got.view(np.uint8).tobytes() == want.view(np.uint8).tobytes()
+    assert_ok(ctx)
+
+
+def test_round_trip_on_gpu(ctx, oracle):
+    import torch
+    say("gpu round trip")
+    x = synth.sinusoids(1 << 20, seed=7)
+    xs = dev(x)
+    s, nb = ctx.compress(xs, 1e-4)
+    torch.cuda.synchronize()
+    y = ctx.decompress(s, x.size, in_bytes=int(nb.item()))
+    torch.cuda.synchronize()
+    y = y.cpu().numpy()
+    assert np.all(np.abs(y.astype(np.float64) - x) <= 1e-4)
+    assert y.tobytes() == oracle.decompress(s[:int(nb.item())].cpu().numpy()).tobytes()
+    assert_ok(ctx)
+
+
+@pytest.mark.parametrize("L", [32, 64, 128])
+def test_fused_matches_oracle(ctx, oracle, L):
+    import torch
+    say("fused", L)
+    n = 6 * 8192 + 333
+    a = synth.sinusoids(n, seed=8)
+    b = np.random.default_rng(9).normal(0, 0.3, n).astype(np.float32)
+    eb = 1e-4
+    s = oracle.compress(a, eb, block_len=L)
+    want = oracle.fused_step(s, b, eb, block_len=L)
+    for tpb in (128, 256):
+        out, nb = ctx.fused_reduce_step(dev(s), dev(b), eb, block_len=L, threads=tpb)
+        torch.cuda.synchronize()
+        got = out[:int(nb.item())].cpu().numpy()
+        assert got.tobytes() == want.tobytes()
+    assert_ok(ctx)
+
+
+def test_fused_minus_zero_identity(ctx):
+    import torch
+    say("fused -0")
+    a = synth.sinusoids(100_000, seed=10)
+    s, nb = ctx.compress(dev(a), 1e-4)
+    torch.cuda.synchronize()
+    s = s[:int(nb.item())]
+    out, nb2 = ctx.fused_reduce_step(s, dev(np.full(a.size, -0.0, np.float32)), 1e-4)
+    torch.cuda.synchronize()
+    assert int(nb2.item()) == s.numel()
+    assert torch.equal(out[:s.numel()], s)
+    assert_ok(ctx)
+
+
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+def test_scatter_matches_oracle(ctx, oracle, dt):
+    import torch
+    say("scatter", dt.__name__)
+    n = 300_000
+    x = synth.sinusoids(n, seed=11).astype(dt)
+    counts, displs = synth.loguniform_counts(n, 23, 50, 40_000, seed=12)
+    want, wcb, wco = oracle.scatter_compress(x, counts, displs, 1e-4, block_len=64)
+    out, cb, co = ctx.scatter_compress(dev(x), counts, displs, 1e-4, block_len=64)
+    torch.cuda.synchronize()
+    cb, co = cb.cpu().numpy(), co.cpu().numpy()
+    assert np.array_equal(cb, wcb.astype(np.int64)) and np.array_equal(co, wco.astype(np.int64))
+    total = int(co[-1] + cb[-1])
+    assert out[:total].cpu().numpy().tobytes() == want.tobytes()
+    # batched decompression of all chunks back into one buffer
+    y = ctx.scatter_decompress(out, torch.from_numpy(co).cuda(), counts, displs,
+                               dtype=torch.float32 if dt == np.float32 else torch.float64,
+                               block_len=64, packed_bytes=total)
+    torch.cuda.synchronize()
+    ref = np.concatenate([oracle.decompress(want[wco[j]:wco[j] + wcb[j]])
+                          for j in range(len(counts))])
+    assert y.cpu().numpy().tobytes() == ref.tobytes()
+    assert_ok(ctx)
+
+
+def _mixed_batch(seed, nreq, max_bytes):
+    reqs = synth.mixed_requests(nreq, seed=seed, lo_bytes=4096, hi_bytes=max_bytes)
+    data = [synth.request_data(r) for r in reqs]
+    Ls = [32, 64, 128]
+    for i, r in enumerate(reqs):
+        r["block_len"] = Ls[i % 3]
+    return reqs, data
+
+
+def test_batch_compress_decompress(ctx, oracle, gz):
+    import torch
+    say("batch")
+    reqs, data = _mixed_batch(1, 60, 256 << 10)
+    ins = [dev(d) for d in data]
+    outs, nbs, items = [], [], []
+    for r, x in zip(reqs, ins):
+        dt = gz.GZ_F32 if r["dtype"] == np.float32 else gz.GZ_F64
+        cap = gz.bound(r["n"], dt, r["block_len"])
+        o = torch.empty(cap, dtype=torch.uint8, device="cuda")
+        nb = torch.zeros(1, dtype=torch.int64, device="cuda")
+        outs.append(o)
+        nbs.append(nb)
+        items.append(dict(**{"in": x}, out=o, out_bytes=nb, n=r["n"], out_cap=cap, eb=r["eb"],
+                          dtype=dt, block_len=r["block_len"]))
+    arr = ctx.requests(items)
+    ctx.batch(gz.GZ_OP_COMPRESS, arr)
+    torch.cuda.synchronize()
+    streams = []
+    for r, d, o, nb in zip(reqs, data, outs, nbs):
+        want = oracle.compress(d, r["eb"], block_len=r["block_len"])
+        got = o[:int(nb.item())].cpu().numpy()
+        assert got.tobytes() == want.tobytes()
+        streams.append(o[:int(nb.item())].clone())
+    # batched decompression
+    ys, items = [], []
+    for r, s in zip(reqs, streams):
+        dt = gz.GZ_F32 if r["dtype"] == np.float32 else gz.GZ_F64
+        y = torch.empty(r["n"], dtype=torch.float32 if dt == gz.GZ_F32 else torch.float64,
+                        device="cuda")
+        ys.append(y)
+        items.append(dict(**{"in": s}, out=y, n=r["n"], in_bytes=s.numel(), dtype=dt,
+                          block_len=r["block_len"]))
+    arr = ctx.requests(items)
+    ctx.batch(gz.GZ_OP_DECOMPRESS, arr)
+    torch.cuda.synchronize()
+    for s, y in zip(streams, ys):
+        assert y.cpu().numpy().tobytes() == oracle.decompress(s.cpu().numpy()).tobytes()
+    assert_ok(ctx)
+
+
+def test_plan_and_graph_replays(ctx, oracle, gz):
+    """A compress plan and a fused plan captured in one graph, replayed
+    several times with eager work in between; every replay matches."""
+    import torch
+    say("plan/graph")
+    n = 70_000
+    a = [synth.sinusoids(n, seed=20 + r) for r in range(3)]
+    eb = 1e-4
+    A = [dev(x) for x in a]
+    cap = gz.bound(n, gz.GZ_F32, 32)
+    S = [torch.empty(cap, dtype=torch.uint8, device="cuda") for _ in range(3)]
+    NB = [torch.zeros(1, dtype=torch.int64, device="cuda") for _ in range(3)]
+    p0 = ctx.plan(gz.GZ_OP_COMPRESS, ctx.requests([dict(**{"in": A[0]}, out=S[0], out_bytes=NB[0],
+                                                         n=n, out_cap=cap, eb=eb, dtype=0)]))
+    p1 = ctx.plan(gz.GZ_OP_FUSED, ctx.requests([dict(**{"in": S[0]}, local=A[1], out=S[1],
+                                                      out_bytes=NB[1], n=n, in_bytes=cap,
+                                                      out_cap=cap, eb=eb, dtype=0)]))
+    p2 = ctx.plan(gz.GZ_OP_FUSED, ctx.requests([dict(**{"in": S[1]}, local=A[2], out=S[2],
+                                                      out_bytes=NB[2], n=n, in_bytes=cap,
+                                                      out_cap=cap, eb=eb, dtype=0)]))
+    g = gz.Graph([p0, p1, p2])
+    s0 = oracle.compress(a[0], eb)
+    s1 = oracle.fused_step(s0, a[1], eb)
+    s2 = oracle.fused_step(s1, a[2], eb)
+    for rep in range(4):
+        for s in S:
+            s.zero_()
+        g.launch()
+        torch.cuda.synchronize()
+        got = S[2][:int(NB[2].item())].cpu().numpy()
+        assert got.tobytes() == s2.tobytes(), rep
+        # eager work between replays
+        ctx.compress(A[1], eb)
+        torch.cuda.synchronize()
+    assert_ok(ctx)
+
+
+@pytest.mark.parametrize("corrupt", ["magic", "n", "reserved_kind", "table", "payload_total",
+                                     "truncated", "pad"])
+def test_corrupt_stream_sets_status(ctx, oracle, corrupt):
+    import torch
+    say("corrupt", corrupt)
+    n = 20_000
+    x = synth.sinusoids(n, seed=30)
+    s = oracle.compress(x, 1e-4).copy()
+    NS = -(-n // 4096)
+    hoff = 64 + 4 * NS
+    ib = s.size
+    if corrupt == "magic":
+        s[0] ^= 1
+    elif corrupt == "n":
+        s[8] ^= 1
+    elif corrupt == "reserved_kind":
+        s[hoff + 5] = 5 << 5
+    elif corrupt == "table":
+        s[64 + 8] ^= 4
+    elif corrupt == "payload_total":
+        s[24] ^= 4
+    elif corrupt == "truncated":
+        ib = s.size - 4
+    elif corrupt == "pad":
+        B = -(-n // 32)
+        s[hoff + B] = 9
+    if corrupt != "n":  # a different n can still be a well-formed stream
+        st, _ = oracle.decompress_status(s[:ib])
+        assert st == oracle.ECORRUPT
+    ctx.decompress(dev(s), n, in_bytes=ib)
+    assert ctx.device_status() == 3  # GZ_ECORRUPT, then cleared
+    y = ctx.decompress(dev(oracle.compress(x, 1e-4)), n)
+    torch.cuda.synchronize()
+    assert ctx.device_status() == 0
+    assert y.cpu().numpy().tobytes() == oracle.decompress(oracle.compress(x, 1e-4)).tobytes()
+
+
+def test_argument_errors(ctx, gz):
+    import torch
+    say("arg errors")
+    x = torch.zeros(100, device="cuda")
+    for eb in (0.0, -1.0, float("nan"), float("inf"), 1e-46):
+        with pytest.raises(gz.GzError) as e:
+            ctx.compress(x, eb)
+        assert e.value.status == gz.GZ_EINVAL
+    with pytest.raises(gz.GzError) as e:
+        ctx.compress(x, 1e-3, out=torch.empty(100, dtype=torch.uint8, device="cuda"))
+    assert e.value.status == gz.GZ_ENOSPC
+    with pytest.raises(gz.GzError) as e:
+        ctx.compress(x, 1e-3, block_len=48)
+    assert e.value.status == gz.GZ_EINVAL
+
+
+def test_quantize_sampled_bit_patterns(ctx, oracle):
+    """Elementwise quantisation of 2^26 bit patterns (stride sample of all
+    2^32 plus dense windows around ties and range edges) equals the oracle
+    for several bounds."""
+    import torch
+    say("quantize sweep")
+    g = np.random.default_rng(31)
+    bits = np.concatenate([
+        (np.arange(1 << 25, dtype=np.uint64) * 128 + g.integers(0, 128, 1 << 25)).astype(np.uint32),
+        g.integers(0, 1 << 32, 1 << 24, dtype=np.uint64).astype(np.uint32),
+        (np.arange(1 << 23, dtype=np.uint32) + np.uint32(0x3F000000)),
+        (np.arange(1 << 23, dtype=np.uint32) + np.uint32(0x4E000000)),
+    ])
+    x = bits.view(np.float32)
+    xd = dev(x)
+    for eb in (1e-4, 1e-3, 2.0 ** -14, 0.37, 3e-30):
+        q, f = ctx.quantize(xd, eb)
+        torch.cuda.synchronize()
+        wq, wf = oracle.quantize(x, eb)
+        assert np.array_equal(f.cpu().numpy().astype(bool), wf)
+        assert np.array_equal(q.cpu().numpy(), wq)
