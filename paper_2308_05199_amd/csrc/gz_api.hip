@@ -65,6 +65,7 @@ struct gz_plan {
   uint32_t* d_map = nullptr;
   uint32_t total = 0;
   uint32_t tpb = 0, grid = 0;
+  bool wide = false;
 };
 
 struct gz_graph {
@@ -467,7 +468,7 @@ gz_status gz_scatter_compress(gz_ctx* c, const void* d_root, gz_dtype dtype,
   if (r != GZ_OK) return r;
   const uint32_t grid = pick_grid(c, 0, dtype, L, tpb, strip, p);
   return hip_status(gzk::launch_batch(0, c->d_jobs, c->d_map, (uint32_t)strip, c->ctl(), tpb,
-                                      grid, st));
+                                      grid, dtype == GZ_F64, st));
 }
 
 gz_status gz_scatter_decompress(gz_ctx* c, const void* d_packed, uint64_t packed_bytes,
@@ -510,7 +511,7 @@ gz_status gz_scatter_decompress(gz_ctx* c, const void* d_packed, uint64_t packed
   if (r != GZ_OK) return r;
   const uint32_t grid = pick_grid(c, 1, dtype, L, tpb, strip, p);
   return hip_status(gzk::launch_batch(1, c->d_jobs, c->d_map, (uint32_t)strip, c->ctl(), tpb,
-                                      grid, st));
+                                      grid, dtype == GZ_F64, st));
 }
 
 gz_status gz_batch(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t nreq,
@@ -525,11 +526,13 @@ gz_status gz_batch(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t nreq,
   hipStream_t st = (hipStream_t)stream;
   r = stage_upload(c, jobs, map, st);
   if (r != GZ_OK) return r;
+  bool wide = false;
+  for (const Job& J : jobs) wide = wide || J.dtype == GZ_F64;
   uint64_t g = (p && p->grid) ? p->grid
-                              : (uint64_t)c->cus * gzk::occupancy_blocks(3, 0, 5, tpb);
+                              : (uint64_t)c->cus * gzk::occupancy_blocks(3, wide, 5, tpb);
   g = std::max<uint64_t>(1, std::min<uint64_t>(g, map.size()));
   return hip_status(gzk::launch_batch((uint32_t)op, c->d_jobs, c->d_map, (uint32_t)map.size(),
-                                      c->ctl(), tpb, (uint32_t)g, st));
+                                      c->ctl(), tpb, (uint32_t)g, wide, st));
 }
 
 gz_status gz_plan_create(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t nreq,
@@ -548,8 +551,9 @@ gz_status gz_plan_create(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t
   pl->op = op;
   pl->total = (uint32_t)map.size();
   pl->tpb = tpb;
+  for (const Job& J : jobs) pl->wide = pl->wide || J.dtype == GZ_F64;
   uint64_t g = (p && p->grid) ? p->grid
-                              : (uint64_t)c->cus * gzk::occupancy_blocks(3, 0, 5, tpb);
+                              : (uint64_t)c->cus * gzk::occupancy_blocks(3, pl->wide, 5, tpb);
   pl->grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(g, map.size()));
   if (hipMalloc((void**)&pl->d_jobs, jobs.size() * sizeof(Job)) != hipSuccess ||
       hipMalloc((void**)&pl->d_map, map.size() * 4) != hipSuccess) {
@@ -569,7 +573,7 @@ gz_status gz_plan_create(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t
 gz_status gz_plan_launch(gz_plan* pl, gz_stream_t stream) {
   if (!pl) return GZ_EINVAL;
   return hip_status(gzk::launch_batch(pl->op, pl->d_jobs, pl->d_map, pl->total, pl->ctx->ctl(),
-                                      pl->tpb, pl->grid, (hipStream_t)stream));
+                                      pl->tpb, pl->grid, pl->wide, (hipStream_t)stream));
 }
 
 void gz_plan_destroy(gz_plan* pl) {

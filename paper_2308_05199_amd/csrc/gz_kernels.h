@@ -9,13 +9,14 @@ namespace gzk {
 // op: 0 compress, 1 decompress, 2 fused step (fp32 only)
 hipError_t launch_single(uint32_t op, const Job& J, const Ctl& C, uint32_t tpb, uint32_t grid,
                          hipStream_t st);
+// wide: the batch holds fp64 jobs (larger LDS staging)
 hipError_t launch_batch(uint32_t op, const Job* d_jobs, const uint32_t* d_strip_job,
-                        uint32_t total, const Ctl& C, uint32_t tpb, uint32_t grid,
+                        uint32_t total, const Ctl& C, uint32_t tpb, uint32_t grid, bool wide,
                         hipStream_t st);
 hipError_t launch_quantize(const void* x, uint64_t n, const Job& J, int32_t* q, uint8_t* fail,
                            hipStream_t st);
 hipError_t launch_reset(const Ctl& C, hipStream_t st);
-// resident workgroups per CU of a kernel (op 3 = batched kernel)
+// resident workgroups per CU of a kernel (op 3 = batched kernel; dtype sizes its LDS)
 int occupancy_blocks(uint32_t op, uint32_t dtype, uint32_t log2L, uint32_t tpb);
 
 }  // namespace gzk

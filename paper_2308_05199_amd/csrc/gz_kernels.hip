@@ -84,25 +84,38 @@ __device__ __forceinline__ uint32_t grp_excl_sum(uint32_t v, uint32_t w) {
 // the IEEE quotient; below the normal range both give q = 0.  x - xh is
 // exact (Sterbenz), so |x - xh| <= eb is tested in float against the largest
 // float not above eb.
+// Saturating conversions (the hardware instructions are defined for every
+// input; the C++ casts are not).
+__device__ __forceinline__ int32_t cvt_sat(float f) {
+  int32_t r;
+  asm("v_cvt_i32_f32 %0, %1" : "=v"(r) : "v"(f));
+  return r;
+}
+__device__ __forceinline__ int32_t cvt_sat(double f) {
+  int32_t r;
+  asm("v_cvt_i32_f64 %0, %1" : "=v"(r) : "v"(f));
+  return r;
+}
+
+// When |r| < 2^29 the rounded value rr is an integer held exactly, so
+// (T)q == rr and xh is formed from rr directly.
 __device__ __forceinline__ int32_t quant(float x, double rinv, float t, float eblo,
                                          bool& bad) {
   float r = (float)((double)x * rinv);
+  float rr = __builtin_rintf(r);
   bool inr = fabsf(r) < 536870912.0f;  // false for NaN
-  float rr = inr ? __builtin_rintf(r) : 0.0f;
-  int32_t q = (int32_t)rr;
-  float xh = (float)q * t;
-  float d = x - xh;
+  int32_t q = cvt_sat(rr);
+  float d = x - rr * t;
   bad = !inr || !(fabsf(d) <= eblo);
   return q;
 }
 
 __device__ __forceinline__ int32_t quant(double x, double t, double eb, bool& bad) {
   double r = x / t;
+  double rr = __builtin_rint(r);
   bool inr = fabs(r) <= 536870911.0;
-  double rr = inr ? __builtin_rint(r) : 0.0;
-  int32_t q = (int32_t)rr;
-  double xh = (double)q * t;
-  double d = x - xh;
+  int32_t q = cvt_sat(rr);
+  double d = x - rr * t;
   bad = !inr || !(fabs(d) <= eb);
   return q;
 }
@@ -204,10 +217,11 @@ __device__ __forceinline__ double from_raw(const uint32_t* src, double) {
 
 // ------------------------------------------------------------- LDS state
 struct Smem {
-  uint32_t ticket;
+  uint32_t cur;                  // strip being processed
   uint32_t epoch;
   uint32_t flag;                 // strip error flags
   uint32_t hdr_ok;
+  uint32_t hdr_job;              // 1 + job whose stream header was checked
   uint32_t wtot[MAX_TPB / 64];
   unsigned long long excl;       // strip exclusive prefix (dwords, chain-wide)
   unsigned long long pj;         // chain prefix at the job's first strip
@@ -217,16 +231,18 @@ struct Smem {
   uint32_t hb[MAX_TPB / 4];      // header bytes of the strip's blocks
 };
 
-__device__ __forceinline__ void prologue(const Ctl& C, Smem& sm) {
-  if (threadIdx.x == 0) sm.epoch = ld_agent32(&C.ctrl->epoch);
-  __syncthreads();
-}
+// Staging buffer for one strip's payload (dynamic LDS): 16 bytes of headroom
+// for realigning the copy-in, TPB*32*sizeof(T) bytes, 16 bytes of tail.
+extern __shared__ __attribute__((aligned(16))) uint32_t g_stage[];
 
-__device__ __forceinline__ uint32_t next_ticket(const Ctl& C, Smem& sm) {
-  __syncthreads();  // everyone is done with the previous strip's LDS
-  if (threadIdx.x == 0) sm.ticket = atomicAdd(&C.ctrl->ticket, 1u);
+__device__ __forceinline__ uint32_t first_ticket(const Ctl& C, Smem& sm) {
+  if (threadIdx.x == 0) {
+    sm.epoch = ld_agent32(&C.ctrl->epoch);
+    sm.hdr_job = 0;
+    sm.cur = atomicAdd(&C.ctrl->ticket, 1u);
+  }
   __syncthreads();
-  return sm.ticket;
+  return sm.cur;
 }
 
 __device__ __forceinline__ void epilogue(const Ctl& C) {
@@ -245,17 +261,19 @@ __device__ __forceinline__ bool aborted(const Ctl& C) {
   return (ld_agent32(&C.ctrl->err) & ERRF_TIMEOUT) != 0;
 }
 
-// Decoupled look-back run by wave 0: publishes the strip aggregate, returns
-// the exclusive prefix (dwords) of strip gs within its chain.
+// Publishes the strip aggregate (or, at the head of a chain, its prefix).
+__device__ __forceinline__ void publish_agg(const Ctl& C, uint64_t gs, uint64_t chain0,
+                                            uint32_t ep, uint64_t agg) {
+  st_agent(C.status + gs, sw_pack(gs == chain0 ? 2 : 1, ep, agg));
+}
+
+// Decoupled look-back run by wave 0 after publish_agg: returns the exclusive
+// prefix (dwords) of strip gs within its chain and publishes its inclusive
+// prefix.  Looks back 64 strips per probe.
 __device__ uint64_t lookback(const Ctl& C, uint64_t gs, uint64_t chain0, uint32_t ep,
                              uint64_t agg, bool& timeout) {
   const int lane = __lane_id();
-  unsigned long long* status = C.status;
-  if (gs == chain0) {
-    if (lane == 0) st_agent(status + gs, sw_pack(2, ep, agg));
-    return 0;
-  }
-  if (lane == 0) st_agent(status + gs, sw_pack(1, ep, agg));
+  if (gs == chain0) return 0;
   uint64_t excl = 0;
   int64_t top = (int64_t)gs - 1;
   uint32_t spins = 0;
@@ -264,7 +282,7 @@ __device__ uint64_t lookback(const Ctl& C, uint64_t gs, uint64_t chain0, uint32_
     uint32_t flag;
     uint64_t val;
     if (idx >= (int64_t)chain0) {
-      uint64_t w = ld_agent(status + idx);
+      uint64_t w = ld_agent(C.status + idx);
       bool cur = (uint32_t)((w >> 34) & 0x0FFFFFFFu) == (ep & 0x0FFFFFFFu);
       flag = cur ? (uint32_t)(w >> 62) : 0u;
       val = w & VMASK;
@@ -282,14 +300,14 @@ __device__ uint64_t lookback(const Ctl& C, uint64_t gs, uint64_t chain0, uint32_
         timeout = true;
         break;
       }
-      __builtin_amdgcn_s_sleep(2);
+      __builtin_amdgcn_s_sleep(1);
       continue;
     }
     excl += wave_sum64(lane <= p ? val : 0ull);
     if (p < 64) break;
     top -= 64;
   }
-  if (lane == 0) st_agent(status + gs, sw_pack(2, ep, timeout ? 0 : excl + agg));
+  if (lane == 0) st_agent(C.status + gs, sw_pack(2, ep, timeout ? 0 : excl + agg));
   return excl;
 }
 
@@ -305,7 +323,7 @@ __device__ uint64_t job_base_wait(const Ctl& C, uint32_t j, uint32_t ep, bool& t
       timeout = true;
       return 0;
     }
-    __builtin_amdgcn_s_sleep(2);
+    __builtin_amdgcn_s_sleep(1);
   }
 }
 
@@ -336,55 +354,64 @@ __device__ __forceinline__ uint32_t plane_of(const uint32_t (&a)[32], uint32_t j
 }
 
 // --------------------------------------------------------------- encode
-// Encodes the strip whose lane values are v[0..vcnt) (mode 0), publishes
-// its look-back word and writes its part of the stream.
-template <typename T, int L>
-__device__ void encode_strip(const Job& J, uint64_t s, uint64_t gs, const Ctl& C, Smem& sm,
-                             const T (&v)[32], uint32_t vcnt, bool skip) {
-  constexpr int LPB = L / 32;
-  constexpr uint32_t ES = sizeof(T);
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const uint32_t TPB = blockDim.x;
-  const uint64_t seg = s * TPB + tid;
-  const uint32_t w = tid & (LPB - 1);
-  const uint64_t b = seg / LPB;
+// Per-lane result of analysing a segment: the block's kind, width and size
+// (identical on the LPB lanes of a block) and this lane's share of the
+// payload (base, sign word, residual magnitudes).
+struct LaneCode {
+  uint32_t a[32];   // |d| of the lane's 32 elements
+  uint32_t sg;      // sign bits
+  int32_t base;     // q of the block's first element (lane w == 0)
+  uint32_t kind, F, size_dw;
+  bool exists;
+};
 
-  // quantise
-  int32_t q[32];
-  bool bad = false, nz = false;
+// Mode 0: 1D blocks of L consecutive elements, L1D prediction.
+template <typename T, int L, bool FULL>
+__device__ __forceinline__ void analyze_1d(const Job& J, uint64_t seg, uint32_t w,
+                                           const T (&v)[32], uint32_t vcnt, LaneCode& lc) {
+  constexpr int LPB = L / 32;
+  constexpr uint32_t EW = sizeof(T) / 4;
+  const uint64_t b = seg / LPB;
+  uint32_t (&a)[32] = lc.a;
+  bool bad = false;
 #pragma unroll
   for (int i = 0; i < 32; ++i) {
     bool bi = false;
     int32_t qi = quant_t<T>(v[i], J, bi);
-    bool valid = i < (int)vcnt;
-    q[i] = valid ? qi : 0;
-    bad |= valid && bi;
-    nz |= valid && qi != 0;
+    if (FULL) {
+      a[i] = (uint32_t)qi;
+      bad |= bi;
+    } else {
+      const bool valid = i < (int)vcnt;
+      a[i] = valid ? (uint32_t)qi : 0u;
+      bad |= valid && bi;
+    }
   }
-  // residuals against the previous element (previous lane for i == 0)
-  int32_t prev = __shfl_up(q[31], 1);
-  uint32_t a[32];
+  // residual magnitudes in place (downwards, so a[i-1] still holds q)
+  const int32_t base = (int32_t)a[0];
+  const int32_t prev = __shfl_up((int32_t)a[31], 1);
   uint32_t sg = 0, orv = 0;
 #pragma unroll
   for (int i = 31; i >= 0; --i) {
-    int32_t pq = i ? q[i - 1] : prev;
-    int32_t d = (i < (int)vcnt) ? (int32_t)((uint32_t)q[i] - (uint32_t)pq) : 0;
+    const int32_t pq = i ? (int32_t)a[i - 1] : prev;
+    int32_t d = (int32_t)(a[i] - (uint32_t)pq);
     if (i == 0 && w == 0) d = 0;
-    uint32_t ad = (uint32_t)(d < 0 ? -d : d);
+    if (!FULL && i >= (int)vcnt) d = 0;
+    const uint32_t ad = (uint32_t)(d < 0 ? -d : d);
     a[i] = ad;
     orv |= ad;
-    sg |= (uint32_t)(d < 0) << i;
+    sg = __builtin_amdgcn_alignbit(sg, (uint32_t)d, 31);
   }
+  const uint32_t nzb = grp_or<LPB>((base != 0 ? 1u : 0u) | orv);
   orv = grp_or<LPB>(orv);
-  uint32_t badb = grp_or<LPB>((uint32_t)bad);
-  uint32_t nzb = grp_or<LPB>((uint32_t)nz);
+  const uint32_t badb = grp_or<LPB>(bad ? 1u : 0u);
 
-  const uint64_t bstart = b * (uint64_t)L;
-  const bool exists = b < J.B;
-  const uint32_t m = exists ? (uint32_t)min((uint64_t)L, J.n - bstart) : 0u;
+  const bool exists = FULL || b < J.B;
+  const uint32_t m = FULL ? (uint32_t)L
+                          : (exists ? (uint32_t)min((uint64_t)L, J.n - b * (uint64_t)L) : 0u);
   uint32_t F = orv ? 32u - (uint32_t)__clz(orv) : 0u;
   uint32_t kind, size_dw;
-  const uint32_t raw_dw = m * (ES / 4);
+  const uint32_t raw_dw = m * EW;
   if (!exists) {
     kind = K_ZERO; size_dw = 0; F = 0;
   } else if (badb) {
@@ -396,11 +423,269 @@ __device__ void encode_strip(const Job& J, uint64_t s, uint64_t gs, const Ctl& C
     size_dw = 1u + (F ? (F + 1u) * LPB : 0u);
     if (size_dw > raw_dw) { kind = K_RAW; size_dw = raw_dw; F = 0; }
   }
-  const uint32_t hbyte = (kind << 5) | F;
+  lc.sg = sg;
+  lc.base = base;
+  lc.kind = kind;
+  lc.F = F;
+  lc.size_dw = size_dw;
+  lc.exists = exists;
+}
+
+// ---- mode 1: 8x8 tiles, two lanes per tile (lane w owns rows 4w..4w+3).
+__device__ __forceinline__ uint32_t bitlen(int32_t v) {
+  const uint32_t a = (uint32_t)(v < 0 ? -v : v);
+  return a ? 32u - (uint32_t)__clz(a) : 0u;
+}
+
+// Tile features (16 int8 bit lengths of sampled values and residuals) as
+// four packed words, identical on both lanes of the tile.
+__device__ __forceinline__ void tile_features(const int32_t (&q)[32], uint32_t w,
+                                              uint32_t (&f)[4]) {
+  // each lane computes 8 features in pairs (g0: f0 f1 | f2 f3, g1: f4 f5 |
+  // f6 f7, g2: f8 f9 | f10 f11, g3: f12 f13 | f14 f15)
+  uint32_t p0, p1, p2, p3;
+  if (w == 0) {  // rows 0..3
+    p0 = bitlen(q[0]) | bitlen(q[21]) << 8;
+    p1 = bitlen(q[9] - q[8]) | bitlen(q[30] - q[29]) << 8;
+    p2 = bitlen(q[11] - q[3]) | bitlen(q[25] - q[17]) << 8;
+    p3 = bitlen(q[13] - q[12] - q[5] + q[4]) | bitlen(q[18] - q[17] - q[10] + q[9]) << 8;
+  } else {       // rows 4..7
+    p0 = bitlen(q[10]) | bitlen(q[31]) << 8;
+    p1 = bitlen(q[3] - q[2]) | bitlen(q[23] - q[22]) << 8;
+    p2 = bitlen(q[14] - q[6]) | bitlen(q[28] - q[20]) << 8;
+    p3 = bitlen(q[13] - q[12] - q[5] + q[4]) | bitlen(q[17] - q[16] - q[9] + q[8]) << 8;
+  }
+  const uint32_t x0 = p0 | p1 << 16, x1 = p2 | p3 << 16;
+  const uint32_t y0 = __shfl_xor(x0, 1), y1 = __shfl_xor(x1, 1);
+  const uint32_t l0 = w ? y0 : x0, l1 = w ? y1 : x1;  // lane 0's pairs
+  const uint32_t h0 = w ? x0 : y0, h1 = w ? x1 : y1;  // lane 1's pairs
+  f[0] = (l0 & 0xFFFFu) | (h0 << 16);
+  f[1] = (l0 >> 16) | (h0 & 0xFFFF0000u);
+  f[2] = (l1 & 0xFFFFu) | (h1 << 16);
+  f[3] = (l1 >> 16) | (h1 & 0xFFFF0000u);
+}
+
+// int8 MLP 16 -> 32 -> 3 on the tile's features; the two lanes of a tile
+// each evaluate 16 hidden units.  Weights come from LDS (blob layout).
+// Returns 0 NONE, 1 L1D, 2 L2D (argmax, lowest index on ties).
+__device__ __forceinline__ uint32_t mlp_choose(const uint32_t (&f)[4], uint32_t w,
+                                               const uint32_t* wts) {
+  const int s = (int)wts[1];
+  const int32_t rnd = s ? (1 << (s - 1)) : 0;
+  const uint32_t* W1 = wts + 2;           // 32 rows x 4 words
+  const int32_t* b1 = (const int32_t*)(wts + 2 + 128);
+  const uint32_t* W2 = wts + 2 + 128 + 32;  // 3 rows x 8 words
+  const int32_t* b2 = (const int32_t*)(wts + 2 + 128 + 32 + 24);
+  uint32_t hp[4];
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    uint32_t packed = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int k = 16 * (int)w + 4 * g + u;
+      int32_t acc = b1[k];
+      acc = __builtin_amdgcn_sdot4((int)W1[4 * k + 0], (int)f[0], acc, false);
+      acc = __builtin_amdgcn_sdot4((int)W1[4 * k + 1], (int)f[1], acc, false);
+      acc = __builtin_amdgcn_sdot4((int)W1[4 * k + 2], (int)f[2], acc, false);
+      acc = __builtin_amdgcn_sdot4((int)W1[4 * k + 3], (int)f[3], acc, false);
+      int32_t h = (acc + rnd) >> s;
+      h = h < 0 ? 0 : (h > 127 ? 127 : h);
+      packed |= (uint32_t)h << (8 * u);
+    }
+    hp[g] = packed;
+  }
+  int32_t lg[3];
+#pragma unroll
+  for (int o = 0; o < 3; ++o) {
+    int32_t acc = 0;
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+      acc = __builtin_amdgcn_sdot4((int)W2[8 * o + 4 * w + g], (int)hp[g], acc, false);
+    lg[o] = acc + __shfl_xor(acc, 1) + b2[o];
+  }
+  uint32_t best = 0;
+  int32_t bv = lg[0];
+  if (lg[1] > bv) { best = 1; bv = lg[1]; }
+  if (lg[2] > bv) { best = 2; }
+  return best;
+}
+
+// Residual of element i of the lane for predictor k (0 NONE, 1 L1D, 2 L2D).
+// up[c] is q of the row above the lane's first row (lane 1 only).
+template <int K>
+__device__ __forceinline__ int32_t tile_res(const int32_t (&q)[32], const int32_t (&up)[8],
+                                            uint32_t w, int i) {
+  const int r = i / 8, c = i % 8;
+  const int32_t x = q[i];
+  if (K == 0) return x;
+  const bool top = (r == 0 && w == 0);  // first row of the tile
+  const int32_t left = c ? q[i - 1] : 0;
+  const int32_t above = r ? q[i - 8] : up[c];
+  if (K == 1) {
+    if (c) return (int32_t)((uint32_t)x - (uint32_t)left);
+    return top ? 0 : (int32_t)((uint32_t)x - (uint32_t)above);
+  }
+  if (top) return c ? (int32_t)((uint32_t)x - (uint32_t)left) : 0;
+  if (!c) return (int32_t)((uint32_t)x - (uint32_t)above);
+  const int32_t diag = r ? q[i - 9] : up[c - 1];
+  return (int32_t)((uint32_t)x - (uint32_t)left - (uint32_t)above + (uint32_t)diag);
+}
+
+template <int K>
+__device__ __forceinline__ uint32_t tile_or(const int32_t (&q)[32], const int32_t (&up)[8],
+                                            uint32_t w) {
+  uint32_t o = 0;
+#pragma unroll
+  for (int i = 0; i < 32; ++i) {
+    const int32_t d = tile_res<K>(q, up, w, i);
+    o |= (uint32_t)(d < 0 ? -d : d);
+  }
+  return grp_or<2>(o);
+}
+
+template <int K>
+__device__ __forceinline__ void tile_mag(int32_t (&q)[32], const int32_t (&up)[8], uint32_t w,
+                                         uint32_t& sg) {
+  sg = 0;
+#pragma unroll
+  for (int i = 31; i >= 0; --i) {  // in place, downwards
+    const int32_t d = tile_res<K>(q, up, w, i);
+    q[i] = d < 0 ? -d : d;
+    sg = __builtin_amdgcn_alignbit(sg, (uint32_t)d, 31);
+  }
+}
+
+__device__ __forceinline__ uint32_t size_of(uint32_t kind, uint32_t F) {
+  const uint32_t planes = F ? (F + 1u) * 2u : 0u;  // L = 64: two words per plane
+  return kind == K_NONE ? planes : 1u + planes;
+}
+
+// Quantised tile values of the lane (used by the trial kernel and mode 1).
+__device__ __forceinline__ void tile_quant(const Job& J, const float (&v)[32], int32_t (&q)[32],
+                                           bool& bad) {
+  bad = false;
+#pragma unroll
+  for (int i = 0; i < 32; ++i) {
+    bool bi = false;
+    q[i] = quant_t<float>(v[i], J, bi);
+    bad |= bi;
+  }
+  bad = grp_or<2>(bad ? 1u : 0u) != 0;
+}
+
+// Mode 1 analysis: exhaustive trial (select 1), MLP (select 0) or L1D only.
+__device__ __forceinline__ void analyze_tile(const Job& J, uint32_t w, const float (&v)[32],
+                                             bool exists, const uint32_t* wts, LaneCode& lc) {
+  int32_t (&q)[32] = *reinterpret_cast<int32_t(*)[32]>(lc.a);
+  bool bad;
+  tile_quant(J, v, q, bad);
+  int32_t up[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) up[c] = __shfl_up(q[24 + c], 1);
+  const int32_t base = q[0];
+  uint32_t pk;  // 0 NONE, 1 L1D, 2 L2D
+  uint32_t orv;
+  if (J.select == 1) {
+    const uint32_t o0 = tile_or<0>(q, up, w), o1 = tile_or<1>(q, up, w), o2 = tile_or<2>(q, up, w);
+    const uint32_t F0 = o0 ? 32u - __clz(o0) : 0u, F1 = o1 ? 32u - __clz(o1) : 0u,
+                   F2 = o2 ? 32u - __clz(o2) : 0u;
+    const uint32_t s0 = size_of(K_NONE, F0), s1 = size_of(K_L1D, F1), s2 = size_of(K_L2D, F2);
+    pk = 0; orv = o0;
+    uint32_t bs = s0;
+    if (s1 < bs) { pk = 1; bs = s1; orv = o1; }
+    if (s2 < bs) { pk = 2; orv = o2; }
+  } else if (J.select == 0) {
+    uint32_t f[4];
+    tile_features(q, w, f);
+    pk = mlp_choose(f, w, wts);
+    orv = pk == 0 ? tile_or<0>(q, up, w) : pk == 1 ? tile_or<1>(q, up, w) : tile_or<2>(q, up, w);
+  } else {
+    pk = 1;
+    orv = tile_or<1>(q, up, w);
+  }
+  uint32_t sg;
+  if (pk == 0) tile_mag<0>(q, up, w, sg);
+  else if (pk == 1) tile_mag<1>(q, up, w, sg);
+  else tile_mag<2>(q, up, w, sg);
+  const uint32_t nzb = grp_or<2>(base != 0 ? 1u : 0u) | orv;
+  uint32_t F = orv ? 32u - (uint32_t)__clz(orv) : 0u;
+  uint32_t kind = pk == 0 ? K_NONE : pk == 1 ? K_L1D : K_L2D;
+  uint32_t size_dw = size_of(kind, F);
+  if (!exists) {
+    kind = K_ZERO; F = 0; size_dw = 0;
+  } else if (bad) {
+    kind = K_RAW; F = 0; size_dw = 64;
+  } else if (!nzb) {
+    kind = K_ZERO; F = 0; size_dw = 0;
+  } else if (size_dw > 64) {
+    kind = K_RAW; F = 0; size_dw = 64;
+  }
+  lc.sg = sg;
+  lc.base = base;
+  lc.kind = kind;
+  lc.F = F;
+  lc.size_dw = size_dw;
+  lc.exists = exists;
+}
+
+// Element i of a lane segment: its offset from the segment's first element.
+template <int MODE>
+__device__ __forceinline__ uint64_t seg_off(const Job& J, int i) {
+  return MODE == 0 ? (uint64_t)i : (uint64_t)(i / 8) * J.nx + (i % 8);
+}
+// First element of segment seg (mode 1: row 4w of tile seg/2).
+template <int MODE>
+__device__ __forceinline__ uint64_t seg_first(const Job& J, uint64_t seg) {
+  if (MODE == 0) return seg * SEG;
+  const uint64_t b = seg >> 1, tpr = J.nx / 8;
+  const uint64_t R = b / tpr, Cc = b - R * tpr;
+  return (8 * R + 4 * (seg & 1)) * J.nx + 8 * Cc;
+}
+
+// Scan, publish, stage, look back and write one strip (any mode).  KEEPV:
+// v stays valid for RAW blocks; otherwise RAW blocks re-read J.in.
+template <typename T, int L, int MODE, bool KEEPV>
+__device__ void emit_strip(const Job& J, uint64_t s, uint64_t gs, const Ctl& C, Smem& sm,
+                           const T (&v)[32], uint32_t vcnt, const LaneCode& lc, bool skip) {
+  constexpr int LPB = L / 32;
+  constexpr uint32_t EW = sizeof(T) / 4;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const uint32_t TPB = blockDim.x;
+  const uint64_t seg = s * TPB + tid;
+  const uint32_t w = tid & (LPB - 1);
+  uint32_t* stage = g_stage + 4;
+  const uint32_t kind = lc.kind, F = lc.F, size_dw = lc.size_dw;
 
   uint32_t total;
-  uint32_t excl_lane = strip_scan(w == 0 ? size_dw : 0u, sm, total);
+  const uint32_t excl_lane = strip_scan(w == 0 ? size_dw : 0u, sm, total);
   const uint32_t boff = (w == 0) ? excl_lane : excl_lane - size_dw;
+  if (tid == 0) publish_agg(C, gs, J.chain0, sm.epoch, total);
+  if (w == 0) ((uint8_t*)sm.hb)[tid / LPB] = (uint8_t)(lc.exists ? ((kind << 5) | F) : 0u);
+
+  // pack the payload into LDS while the predecessors resolve
+  uint32_t* st = stage + boff;
+  if (kind == K_L1D || kind == K_L2D || kind == K_NONE) {
+    uint32_t o = 0;
+    if (kind != K_NONE) {
+      if (w == 0) st[0] = (uint32_t)lc.base;
+      o = 1;
+    }
+    if (F) {
+      st[o + w] = lc.sg;
+      for (uint32_t j = 0; j < F; ++j) st[o + (j + 1) * LPB + w] = plane_of(lc.a, j);
+    }
+  } else if (kind == K_RAW) {
+    const T* src = (const T*)J.in + seg_first<MODE>(J, seg);
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+      if (i < (int)vcnt) {
+        uint32_t wd[2];
+        raw_words(KEEPV ? v[i] : src[seg_off<MODE>(J, i)], wd);
+        st[(w * 32 + i) * EW] = wd[0];
+        if (EW == 2) st[(w * 32 + i) * EW + 1] = wd[1];
+      }
+    }
+  }
 
   if (wid == 0) {
     bool to = false;
@@ -421,38 +706,17 @@ __device__ void encode_strip(const Job& J, uint64_t s, uint64_t gs, const Ctl& C
       if (to) atomicOr(&C.ctrl->err, ERRF_TIMEOUT);
     }
   }
-  // header bytes of this strip's blocks
-  if (w == 0) ((uint8_t*)sm.hb)[tid / LPB] = (uint8_t)(exists ? hbyte : 0u);
   __syncthreads();
   if (sm.flag || skip) return;
 
   const uint64_t pj = sm.pj;
   const uint64_t erel = sm.excl - pj;  // strip offset inside this job's payload
   uint8_t* base8 = (uint8_t*)J.out + J.fixed_off + 4 * pj;
-  uint32_t* pay = (uint32_t*)(base8 + J.pay_off) + erel + boff;
+  uint32_t* dst = (uint32_t*)(base8 + J.pay_off) + erel;
+  for (uint32_t k = tid; k < total; k += TPB) dst[k] = stage[k];
 
-  if (exists && (seg & (SUPER / SEG - 1)) == 0)
+  if (lc.exists && (seg & (SUPER / SEG - 1)) == 0)
     ((uint32_t*)(base8 + HDR))[seg / (SUPER / SEG)] = (uint32_t)(erel + boff);
-
-  if (exists) {
-    if (kind == K_L1D) {
-      if (w == 0) pay[0] = (uint32_t)q[0];
-      if (F) {
-        pay[1 + w] = sg;
-        for (uint32_t j = 0; j < F; ++j) pay[1 + (j + 1) * LPB + w] = plane_of(a, j);
-      }
-    } else if (kind == K_RAW) {
-#pragma unroll
-      for (int i = 0; i < 32; ++i) {
-        if (i < (int)vcnt) {
-          uint32_t wd[2];
-          raw_words(v[i], wd);
-          pay[(w * 32 + i) * (ES / 4)] = wd[0];
-          if (ES == 8) pay[(w * 32 + i) * (ES / 4) + 1] = wd[1];
-        }
-      }
-    }
-  }
   // header bytes as whole words (the strip starts on a 4-block boundary)
   const uint32_t nblk = TPB / LPB;
   const uint64_t blk0 = s * (uint64_t)nblk;
@@ -486,6 +750,17 @@ __device__ void encode_strip(const Job& J, uint64_t s, uint64_t gs, const Ctl& C
   }
 }
 
+// Mode 0 strip encode (FULL: the strip lies entirely inside n).
+template <typename T, int L, bool FULL, bool KEEPV>
+__device__ __forceinline__ void encode_strip(const Job& J, uint64_t s, uint64_t gs, const Ctl& C,
+                                             Smem& sm, const T (&v)[32], uint32_t vcnt,
+                                             bool skip) {
+  const uint64_t seg = s * blockDim.x + threadIdx.x;
+  LaneCode lc;
+  analyze_1d<T, L, FULL>(J, seg, threadIdx.x & (L / 32 - 1), v, vcnt, lc);
+  emit_strip<T, L, 0, KEEPV>(J, s, gs, C, sm, v, vcnt, lc, skip);
+}
+
 // --------------------------------------------------------------- decode
 // Checks the stream header against the job; sets sm.hdr_ok, sm.paydw, sm.t*.
 __device__ void check_header(const Job& J, const uint8_t* in, uint64_t in_bytes, Smem& sm) {
@@ -493,7 +768,6 @@ __device__ void check_header(const Job& J, const uint8_t* in, uint64_t in_bytes,
   if (tid < 64) {
     const bool readable = in_bytes >= HDR;
     uint32_t wv = (tid < 16 && readable) ? ((const uint32_t*)in)[tid] : 0u;
-    uint32_t expect = 0;
     bool ok = true;
     switch (tid) {
       case 0: ok = wv == 0x31435A47u; break;
@@ -504,7 +778,7 @@ __device__ void check_header(const Job& J, const uint8_t* in, uint64_t in_bytes,
       case 9: ok = wv == J.nx; break;
       case 10: ok = wv == SUPER; break;
       case 4: case 5: case 6: case 7: ok = true; break;
-      default: ok = wv == expect; break;
+      default: ok = wv == 0u; break;
     }
     uint64_t okm = __ballot(ok);
     const uint32_t e0 = __shfl(wv, 4), e1 = __shfl(wv, 5);
@@ -524,6 +798,7 @@ __device__ void check_header(const Job& J, const uint8_t* in, uint64_t in_bytes,
       sm.t32 = t32;
       sm.t64 = t64;
       sm.paydw = payload / 4;
+      sm.hdr_job = J.job + 1;
     }
   }
   __syncthreads();
@@ -536,71 +811,111 @@ __device__ __forceinline__ float step_of<float>(const Smem& sm) { return sm.t32;
 template <>
 __device__ __forceinline__ double step_of<double>(const Smem& sm) { return sm.t64; }
 
+// Copies payload dwords [src, src + P) into LDS with 16-byte loads; returns
+// the LDS address of src[0].  Only bytes inside [lo, src + 4P) are read,
+// where lo <= src is readable stream memory.
+__device__ __forceinline__ const uint32_t* copy_in(const uint32_t* src, uint32_t P) {
+  const uint32_t tid = threadIdx.x, TPB = blockDim.x;
+  const uintptr_t a = (uintptr_t)src;
+  const uint32_t delta = (uint32_t)((a & 15u) >> 2);
+  const u4u* al = (const u4u*)(a - 4 * delta);
+  const uint32_t nch = (delta + P + 3) / 4;  // 16-byte chunks touched
+  const uint32_t full = (delta + P) / 4;     // chunks entirely inside
+  u4u* dstc = (u4u*)g_stage;
+  for (uint32_t k0 = 0; k0 < nch; k0 += 4 * TPB) {
+    u4u r[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t k = k0 + u * TPB + tid;
+      if (k < full) {
+        r[u] = al[k];
+      } else if (k < nch) {
+        const uint32_t* p = (const uint32_t*)(al + k);
+        const uint32_t lim = delta + P - 4 * k;  // valid dwords in this chunk
+        r[u].x = lim > 0 ? p[0] : 0u;
+        r[u].y = lim > 1 ? p[1] : 0u;
+        r[u].z = lim > 2 ? p[2] : 0u;
+        r[u].w = 0u;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t k = k0 + u * TPB + tid;
+      if (k < nch) dstc[k] = r[u];
+    }
+  }
+  return g_stage + delta;
+}
+
 // Decodes the lane's segment of strip s of the stream at `in` into v[];
 // returns false (and flags the context) if the strip is malformed.
-template <typename T, int L>
+template <typename T, int L, bool FULL>
 __device__ bool decode_strip(const Job& J, const uint8_t* in, uint64_t in_bytes, uint64_t s,
-                             const Ctl& C, Smem& sm, T (&v)[32], uint32_t& vcnt) {
+                             const Ctl& C, Smem& sm, T (&v)[32], uint32_t vcnt) {
   constexpr int LPB = L / 32;
-  constexpr uint32_t ES = sizeof(T);
+  constexpr uint32_t EW = sizeof(T) / 4;
   const int tid = threadIdx.x;
   const uint32_t TPB = blockDim.x;
   const uint64_t seg = s * TPB + tid;
   const uint32_t w = tid & (LPB - 1);
   const uint64_t b = seg / LPB;
-  const uint64_t e0 = seg * SEG;
-  vcnt = e0 >= J.n ? 0u : (uint32_t)min((uint64_t)SEG, J.n - e0);
 
-  check_header(J, in, in_bytes, sm);
+  if (sm.hdr_job != J.job + 1) check_header(J, in, in_bytes, sm);
+  const bool ok = sm.hdr_ok != 0;
   const uint64_t pay_dw = sm.paydw;
-  bool ok = sm.hdr_ok != 0;
-  __syncthreads();
 
-  const bool exists = b < J.B;
-  const uint32_t m = exists ? (uint32_t)min((uint64_t)L, J.n - b * (uint64_t)L) : 0u;
-  uint32_t hb = (ok && exists) ? (uint32_t)in[J.hdr_off + b] : 0u;
-  uint32_t kind = hb >> 5, F = hb & 31u;
+  // strip payload range from the superblock table
+  const uint32_t* table = (const uint32_t*)(in + HDR);
+  const uint64_t sb0 = s * (uint64_t)(TPB * SEG / SUPER);
+  const uint64_t sbn = sb0 + TPB * SEG / SUPER;
+  uint64_t E = 0, En = 0;
+  if (ok) {
+    E = sb0 < J.NS ? table[sb0] : pay_dw;
+    En = sbn < J.NS ? table[sbn] : pay_dw;
+  }
+  const bool rng = ok && E <= En && En <= pay_dw && En - E <= (uint64_t)TPB * SEG * EW;
+  const uint32_t P = rng ? (uint32_t)(En - E) : 0u;
+  const uint32_t* S = g_stage + 4;
+  if (rng) S = copy_in((const uint32_t*)(in + J.pay_off) + E, P);
+
+  const bool exists = FULL || b < J.B;
+  const uint32_t m = FULL ? (uint32_t)L
+                          : (exists ? (uint32_t)min((uint64_t)L, J.n - b * (uint64_t)L) : 0u);
+  const uint32_t hb = (rng && exists) ? (uint32_t)in[J.hdr_off + b] : 0u;
+  const uint32_t kind = hb >> 5, F = hb & 31u;
   uint32_t size_dw = 0;
   bool hv = true;
   if (kind == K_ZERO) hv = F == 0;
-  else if (kind == K_RAW) { hv = F == 0; size_dw = m * (ES / 4); }
+  else if (kind == K_RAW) { hv = F == 0; size_dw = m * EW; }
   else if (kind == K_L1D) size_dw = 1u + (F ? (F + 1u) * LPB : 0u);
   else hv = false;
   if (!hv) size_dw = 0;
 
   uint32_t total;
-  uint32_t excl_lane = strip_scan(w == 0 ? size_dw : 0u, sm, total);
+  const uint32_t excl_lane = strip_scan(w == 0 ? size_dw : 0u, sm, total);
   const uint32_t boff = (w == 0) ? excl_lane : excl_lane - size_dw;
-  const uint32_t* table = (const uint32_t*)(in + HDR);
-  const uint64_t sb0 = s * (uint64_t)(TPB * SEG / SUPER);
-  const uint64_t E = (ok && sb0 < J.NS) ? table[sb0] : 0u;
-  bool good = hv;
-  if (ok && exists && (seg & (SUPER / SEG - 1)) == 0)
-    good = good && (uint64_t)table[seg / (SUPER / SEG)] == E + boff;
-  if (ok && tid == 0) {
-    const uint64_t sbn = sb0 + TPB * SEG / SUPER;
-    const uint64_t end = E + total;
-    good = good && end <= pay_dw && (sbn < J.NS ? (uint64_t)table[sbn] == end : end == pay_dw);
-    if (s == 0) good = good && E == 0;
-  }
-  if (ok && s == J.nstrips - 1 && tid < 4) {
+  bool good = rng && hv && total == P;
+  if (good && exists && (seg & (SUPER / SEG - 1)) == 0)
+    good = (uint64_t)table[seg / (SUPER / SEG)] == E + boff;
+  if (s == 0) good = good && E == 0;
+  if (rng && s == J.nstrips - 1 && tid < 4) {
     const uint64_t pb = J.B + tid;
     if (pb < ((J.B + 3) & ~3ull)) good = good && in[J.hdr_off + pb] == 0;
   }
-  good = __syncthreads_and(good ? 1 : 0) != 0;
-  if (!ok || !good) {
+  good = __syncthreads_and(good ? 1 : 0) != 0;  // also completes the copy-in
+  if (!good) {
     if (tid == 0) atomicOr(&C.ctrl->err, ERRF_CORRUPT);
 #pragma unroll
     for (int i = 0; i < 32; ++i) v[i] = (T)0;
     return false;
   }
 
-  const uint32_t* pay = (const uint32_t*)(in + J.pay_off) + E + boff;
+  const uint32_t* pw = S + boff;
   const T t = step_of<T>(sm);
   if (kind == K_RAW) {
 #pragma unroll
     for (int i = 0; i < 32; ++i)
-      v[i] = (i < (int)vcnt) ? from_raw(pay + (w * 32 + i) * (ES / 4), T()) : (T)0;
+      v[i] = (FULL || i < (int)vcnt) ? from_raw(pw + (w * 32 + i) * EW, T()) : (T)0;
     return true;
   }
   if (kind == K_ZERO || !exists) {
@@ -609,146 +924,161 @@ __device__ bool decode_strip(const Job& J, const uint8_t* in, uint64_t in_bytes,
     return true;
   }
   // L1D
-  const int32_t base = (int32_t)pay[0];
+  const int32_t base = (int32_t)pw[0];
   uint32_t a[32];
 #pragma unroll
   for (int i = 0; i < 32; ++i) a[i] = 0;
   uint32_t sg = 0;
   if (F) {
-    sg = pay[1 + w];
+    sg = pw[1 + w];
     for (uint32_t j = 0; j < F; ++j) {
-      uint32_t pw = pay[1 + (j + 1) * LPB + w];
+      const uint32_t p = pw[1 + (j + 1) * LPB + w];
 #pragma unroll
-      for (int i = 0; i < 32; ++i) a[i] |= ((pw >> i) & 1u) << j;
+      for (int i = 0; i < 32; ++i) a[i] |= ((p >> i) & 1u) << j;
     }
   }
   uint32_t acc = 0;
 #pragma unroll
   for (int i = 0; i < 32; ++i) {
-    uint32_t neg = 0u - ((sg >> i) & 1u);
+    const uint32_t neg = (uint32_t)__builtin_amdgcn_sbfe((int32_t)sg, i, 1);  // 0 or ~0
     uint32_t d = (a[i] ^ neg) - neg;
     if (i == 0 && w == 0) d = 0;
     acc += d;
     a[i] = acc;  // local prefix
   }
-  const uint32_t carry = grp_excl_sum<LPB>(acc, w);
+  const uint32_t carry = grp_excl_sum<LPB>(acc, w) + (uint32_t)base;
 #pragma unroll
-  for (int i = 0; i < 32; ++i) {
-    int32_t qi = (int32_t)((uint32_t)base + carry + a[i]);
-    v[i] = (T)qi * t;
-  }
+  for (int i = 0; i < 32; ++i) v[i] = (T)(int32_t)(carry + a[i]) * t;
   return true;
 }
 
 // ---------------------------------------------------------------- kernels
+template <typename T, int L, bool FULL>
+__device__ __forceinline__ void compress_body(const Job& J, uint64_t s, uint64_t gs,
+                                              const Ctl& C, Smem& sm) {
+  const uint64_t seg = s * blockDim.x + threadIdx.x;
+  const uint64_t e0 = seg * SEG;
+  const uint32_t vcnt = FULL ? 32u : (e0 >= J.n ? 0u : (uint32_t)min((uint64_t)SEG, J.n - e0));
+  T v[32];
+  load_seg<T>((const T*)J.in + (vcnt ? e0 : 0), vcnt, v);
+  encode_strip<T, L, FULL, false>(J, s, gs, C, sm, v, vcnt, false);
+}
+
 template <typename T, int L>
 __device__ __forceinline__ void compress_one(const Job& J, uint64_t s, uint64_t gs,
                                              const Ctl& C, Smem& sm) {
-  const uint64_t seg = s * blockDim.x + threadIdx.x;
-  const uint64_t e0 = seg * SEG;
-  const uint32_t vcnt = e0 >= J.n ? 0u : (uint32_t)min((uint64_t)SEG, J.n - e0);
+  if ((s + 1) * blockDim.x * SEG <= J.n) compress_body<T, L, true>(J, s, gs, C, sm);
+  else compress_body<T, L, false>(J, s, gs, C, sm);
+}
+
+template <typename T, int L, bool FULL>
+__device__ __forceinline__ void decompress_body(const Job& J, uint64_t s, const Ctl& C,
+                                                Smem& sm) {
+  const uint64_t off = J.in_off ? J.in_off[J.job] : 0ull;
+  const uint8_t* in = (const uint8_t*)J.in + off;
+  const uint64_t avail = off <= J.in_bytes ? J.in_bytes - off : 0ull;
+  const uint64_t e0 = (s * blockDim.x + threadIdx.x) * SEG;
+  const uint32_t vcnt = FULL ? 32u : (e0 >= J.n ? 0u : (uint32_t)min((uint64_t)SEG, J.n - e0));
   T v[32];
-  load_seg<T>((const T*)J.in + (vcnt ? e0 : 0), vcnt, v);
-  encode_strip<T, L>(J, s, gs, C, sm, v, vcnt, false);
+  if (decode_strip<T, L, FULL>(J, in, avail, s, C, sm, v, vcnt)) {
+    if (vcnt) store_seg<T>((T*)J.out + e0, vcnt, v);
+  }
 }
 
 template <typename T, int L>
 __device__ __forceinline__ void decompress_one(const Job& J, uint64_t s, const Ctl& C,
                                                Smem& sm) {
-  const uint64_t off = J.in_off ? J.in_off[J.job] : 0ull;
-  const uint8_t* in = (const uint8_t*)J.in + off;
-  const uint64_t avail = off <= J.in_bytes ? J.in_bytes - off : 0ull;
-  T v[32];
-  uint32_t vcnt;
-  if (decode_strip<T, L>(J, in, avail, s, C, sm, v, vcnt)) {
-    const uint64_t e0 = (s * blockDim.x + threadIdx.x) * SEG;
-    if (vcnt) store_seg<T>((T*)J.out + e0, vcnt, v);
-  }
+  if ((s + 1) * blockDim.x * SEG <= J.n) decompress_body<T, L, true>(J, s, C, sm);
+  else decompress_body<T, L, false>(J, s, C, sm);
 }
 
-template <int L>
-__device__ __forceinline__ void fused_one(const Job& J, uint64_t s, uint64_t gs,
-                                          const Ctl& C, Smem& sm) {
-  float v[32];
-  uint32_t vcnt;
-  bool ok = decode_strip<float, L>(J, (const uint8_t*)J.in, J.in_bytes, s, C, sm, v, vcnt);
+template <int L, bool FULL>
+__device__ __forceinline__ void fused_body(const Job& J, uint64_t s, uint64_t gs, const Ctl& C,
+                                           Smem& sm) {
   const uint64_t e0 = (s * blockDim.x + threadIdx.x) * SEG;
+  const uint32_t vcnt = FULL ? 32u : (e0 >= J.n ? 0u : (uint32_t)min((uint64_t)SEG, J.n - e0));
   float a[32];
-  load_seg<float>(J.local + (vcnt ? e0 : 0), vcnt, a);
+  load_seg<float>(J.local + (vcnt ? e0 : 0), vcnt, a);  // in flight during the decode
+  float v[32];
+  const bool ok = decode_strip<float, L, FULL>(J, (const uint8_t*)J.in, J.in_bytes, s, C, sm,
+                                               v, vcnt);
 #pragma unroll
   for (int i = 0; i < 32; ++i) v[i] = v[i] + a[i];  // incoming + local, fp32
-  encode_strip<float, L>(J, s, gs, C, sm, v, vcnt, !ok);
-}
-
-template <typename T, int L>
-__global__ __launch_bounds__(MAX_TPB) void k_compress(Job J, Ctl C) {
-  __shared__ Smem sm;
-  prologue(C, sm);
-  for (;;) {
-    uint32_t t = next_ticket(C, sm);
-    if (t >= J.nstrips) break;
-    compress_one<T, L>(J, t, t, C, sm);
-  }
-  epilogue(C);
-}
-
-template <typename T, int L>
-__global__ __launch_bounds__(MAX_TPB) void k_decompress(Job J, Ctl C) {
-  __shared__ Smem sm;
-  prologue(C, sm);
-  for (;;) {
-    uint32_t t = next_ticket(C, sm);
-    if (t >= J.nstrips) break;
-    decompress_one<T, L>(J, t, C, sm);
-  }
-  epilogue(C);
+  encode_strip<float, L, FULL, true>(J, s, gs, C, sm, v, vcnt, !ok);
 }
 
 template <int L>
-__global__ __launch_bounds__(MAX_TPB) void k_fused(Job J, Ctl C) {
-  __shared__ Smem sm;
-  prologue(C, sm);
-  for (;;) {
-    uint32_t t = next_ticket(C, sm);
-    if (t >= J.nstrips) break;
-    fused_one<L>(J, t, t, C, sm);
-  }
+__device__ __forceinline__ void fused_one(const Job& J, uint64_t s, uint64_t gs, const Ctl& C,
+                                          Smem& sm) {
+  if ((s + 1) * blockDim.x * SEG <= J.n) fused_body<L, true>(J, s, gs, C, sm);
+  else fused_body<L, false>(J, s, gs, C, sm);
+}
+
+// Persistent loop: the next ticket is requested while the current strip is
+// processed, so the atomic's latency is hidden.
+#define GZ_STRIP_LOOP(TOTAL, BODY)                                      \
+  __shared__ Smem sm;                                                   \
+  uint32_t t = first_ticket(C, sm);                                     \
+  while (t < (TOTAL)) {                                                 \
+    uint32_t nxt = 0;                                                   \
+    if (threadIdx.x == 0) nxt = atomicAdd(&C.ctrl->ticket, 1u);         \
+    BODY;                                                               \
+    __syncthreads();                                                    \
+    if (threadIdx.x == 0) sm.cur = nxt;                                 \
+    __syncthreads();                                                    \
+    t = sm.cur;                                                         \
+  }                                                                     \
   epilogue(C);
+
+#define GZ_KERNEL_ATTR __launch_bounds__(MAX_TPB) __attribute__((amdgpu_waves_per_eu(4, 8)))
+
+template <typename T, int L>
+__global__ GZ_KERNEL_ATTR void k_compress(Job J, Ctl C) {
+  GZ_STRIP_LOOP(J.nstrips, (compress_one<T, L>(J, t, t, C, sm)))
+}
+
+template <typename T, int L>
+__global__ GZ_KERNEL_ATTR void k_decompress(Job J, Ctl C) {
+  GZ_STRIP_LOOP(J.nstrips, (decompress_one<T, L>(J, t, C, sm)))
+}
+
+template <int L>
+__global__ GZ_KERNEL_ATTR void k_fused(Job J, Ctl C) {
+  GZ_STRIP_LOOP(J.nstrips, (fused_one<L>(J, t, t, C, sm)))
 }
 
 // Batched: strip_job maps a global strip to its job.
-__global__ __launch_bounds__(MAX_TPB) void k_batch(const Job* __restrict__ jobs,
-                                                  const uint32_t* __restrict__ strip_job,
-                                                  uint32_t total, uint32_t op, Ctl C) {
-  __shared__ Smem sm;
-  prologue(C, sm);
-  for (;;) {
-    uint32_t t = next_ticket(C, sm);
-    if (t >= total) break;
-    const uint32_t j = strip_job[t];
-    const Job J = jobs[j];
-    const uint64_t s = t - J.strip0;
-    const uint32_t key = (op << 4) | (J.dtype << 3) | J.log2L;
-    switch (key) {
-      case (0u << 4) | (0u << 3) | 5u: compress_one<float, 32>(J, s, t, C, sm); break;
-      case (0u << 4) | (0u << 3) | 6u: compress_one<float, 64>(J, s, t, C, sm); break;
-      case (0u << 4) | (0u << 3) | 7u: compress_one<float, 128>(J, s, t, C, sm); break;
-      case (0u << 4) | (1u << 3) | 5u: compress_one<double, 32>(J, s, t, C, sm); break;
-      case (0u << 4) | (1u << 3) | 6u: compress_one<double, 64>(J, s, t, C, sm); break;
-      case (0u << 4) | (1u << 3) | 7u: compress_one<double, 128>(J, s, t, C, sm); break;
-      case (1u << 4) | (0u << 3) | 5u: decompress_one<float, 32>(J, s, C, sm); break;
-      case (1u << 4) | (0u << 3) | 6u: decompress_one<float, 64>(J, s, C, sm); break;
-      case (1u << 4) | (0u << 3) | 7u: decompress_one<float, 128>(J, s, C, sm); break;
-      case (1u << 4) | (1u << 3) | 5u: decompress_one<double, 32>(J, s, C, sm); break;
-      case (1u << 4) | (1u << 3) | 6u: decompress_one<double, 64>(J, s, C, sm); break;
-      case (1u << 4) | (1u << 3) | 7u: decompress_one<double, 128>(J, s, C, sm); break;
-      case (2u << 4) | (0u << 3) | 5u: fused_one<32>(J, s, t, C, sm); break;
-      case (2u << 4) | (0u << 3) | 6u: fused_one<64>(J, s, t, C, sm); break;
-      case (2u << 4) | (0u << 3) | 7u: fused_one<128>(J, s, t, C, sm); break;
-      default: break;
-    }
+__device__ __forceinline__ void batch_body(const Job* __restrict__ jobs,
+                                           const uint32_t* __restrict__ strip_job, uint32_t t,
+                                           uint32_t op, const Ctl& C, Smem& sm) {
+  const uint32_t j = strip_job[t];
+  const Job J = jobs[j];
+  const uint64_t s = t - J.strip0;
+  const uint32_t key = (op << 4) | (J.dtype << 3) | J.log2L;
+  switch (key) {
+    case (0u << 4) | (0u << 3) | 5u: compress_one<float, 32>(J, s, t, C, sm); break;
+    case (0u << 4) | (0u << 3) | 6u: compress_one<float, 64>(J, s, t, C, sm); break;
+    case (0u << 4) | (0u << 3) | 7u: compress_one<float, 128>(J, s, t, C, sm); break;
+    case (0u << 4) | (1u << 3) | 5u: compress_one<double, 32>(J, s, t, C, sm); break;
+    case (0u << 4) | (1u << 3) | 6u: compress_one<double, 64>(J, s, t, C, sm); break;
+    case (0u << 4) | (1u << 3) | 7u: compress_one<double, 128>(J, s, t, C, sm); break;
+    case (1u << 4) | (0u << 3) | 5u: decompress_one<float, 32>(J, s, C, sm); break;
+    case (1u << 4) | (0u << 3) | 6u: decompress_one<float, 64>(J, s, C, sm); break;
+    case (1u << 4) | (0u << 3) | 7u: decompress_one<float, 128>(J, s, C, sm); break;
+    case (1u << 4) | (1u << 3) | 5u: decompress_one<double, 32>(J, s, C, sm); break;
+    case (1u << 4) | (1u << 3) | 6u: decompress_one<double, 64>(J, s, C, sm); break;
+    case (1u << 4) | (1u << 3) | 7u: decompress_one<double, 128>(J, s, C, sm); break;
+    case (2u << 4) | (0u << 3) | 5u: fused_one<32>(J, s, t, C, sm); break;
+    case (2u << 4) | (0u << 3) | 6u: fused_one<64>(J, s, t, C, sm); break;
+    case (2u << 4) | (0u << 3) | 7u: fused_one<128>(J, s, t, C, sm); break;
+    default: break;
   }
-  epilogue(C);
+}
+
+__global__ GZ_KERNEL_ATTR void k_batch(const Job* __restrict__ jobs,
+                                       const uint32_t* __restrict__ strip_job, uint32_t total,
+                                       uint32_t op, Ctl C) {
+  GZ_STRIP_LOOP(total, (batch_body(jobs, strip_job, t, op, C, sm)))
 }
 
 // Elementwise quantisation (verification entry point).
@@ -774,22 +1104,29 @@ __global__ void k_reset(Ctl C) {
 }
 
 // ------------------------------------------------------------ launchers
+// Dynamic LDS: the strip staging buffer (largest strip payload + headroom).
+static size_t stage_bytes(uint32_t dtype, uint32_t tpb) {
+  return 32 + (size_t)tpb * SEG * (dtype == 0 ? 4 : 8);
+}
+
 template <typename T, int L>
 static hipError_t launch_c(const Job& J, const Ctl& C, uint32_t tpb, uint32_t grid,
                            hipStream_t st) {
-  hipLaunchKernelGGL((k_compress<T, L>), dim3(grid), dim3(tpb), 0, st, J, C);
+  hipLaunchKernelGGL((k_compress<T, L>), dim3(grid), dim3(tpb), stage_bytes(J.dtype, tpb), st, J,
+                     C);
   return hipGetLastError();
 }
 template <typename T, int L>
 static hipError_t launch_d(const Job& J, const Ctl& C, uint32_t tpb, uint32_t grid,
                            hipStream_t st) {
-  hipLaunchKernelGGL((k_decompress<T, L>), dim3(grid), dim3(tpb), 0, st, J, C);
+  hipLaunchKernelGGL((k_decompress<T, L>), dim3(grid), dim3(tpb), stage_bytes(J.dtype, tpb), st,
+                     J, C);
   return hipGetLastError();
 }
 template <int L>
 static hipError_t launch_f(const Job& J, const Ctl& C, uint32_t tpb, uint32_t grid,
                            hipStream_t st) {
-  hipLaunchKernelGGL((k_fused<L>), dim3(grid), dim3(tpb), 0, st, J, C);
+  hipLaunchKernelGGL((k_fused<L>), dim3(grid), dim3(tpb), stage_bytes(0, tpb), st, J, C);
   return hipGetLastError();
 }
 
@@ -825,9 +1162,11 @@ hipError_t launch_single(uint32_t op, const Job& J, const Ctl& C, uint32_t tpb, 
 }
 
 hipError_t launch_batch(uint32_t op, const Job* d_jobs, const uint32_t* d_strip_job,
-                        uint32_t total, const Ctl& C, uint32_t tpb, uint32_t grid,
+                        uint32_t total, const Ctl& C, uint32_t tpb, uint32_t grid, bool wide,
                         hipStream_t st) {
-  hipLaunchKernelGGL(k_batch, dim3(grid), dim3(tpb), 0, st, d_jobs, d_strip_job, total, op, C);
+  // batches holding fp64 jobs stage for the wider type
+  hipLaunchKernelGGL(k_batch, dim3(grid), dim3(tpb), stage_bytes(wide ? 1 : 0, tpb), st, d_jobs,
+                     d_strip_job, total, op, C);
   return hipGetLastError();
 }
 
@@ -881,7 +1220,8 @@ int occupancy_blocks(uint32_t op, uint32_t dtype, uint32_t log2L, uint32_t tpb) 
     f = (const void*)k_batch;
   }
   if (!f) return 1;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, (int)tpb, 0) != hipSuccess || nb < 1)
+  const size_t lds = stage_bytes(op == 2 ? 0 : dtype, tpb);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, (int)tpb, lds) != hipSuccess || nb < 1)
     nb = 1;
   return nb;
 }
