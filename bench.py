@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-headline", action="store_true", help="skip the 1 GiB compress/decompress")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first run a plain 1 GiB device copy (scales profiler byte counters)")
     return ap.parse_args()
 
 
@@ -136,6 +138,14 @@ def main():
     from paper_2308_05199_amd.ring import RingReduceScatter
 
     torch.cuda.set_device(0)
+    if args.calib_copy:
+        a = torch.ones(1 << 28, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        log("calibration copy: 3 x 1 GiB device-to-device")
     log("generating 8 x 256^3 ranks")
     bufs_np = synth.ring_ranks(N_RANKS, SHAPE, seed=0)
     eb = synth.relative_eb(bufs_np, 1e-4)
