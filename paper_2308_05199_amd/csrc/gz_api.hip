@@ -529,7 +529,7 @@ gz_status gz_batch(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t nreq,
   bool wide = false;
   for (const Job& J : jobs) wide = wide || J.dtype == GZ_F64;
   uint64_t g = (p && p->grid) ? p->grid
-                              : (uint64_t)c->cus * gzk::occupancy_blocks(3, wide, 5, tpb);
+                              : (uint64_t)c->cus * gzk::occupancy_blocks(3 + (uint32_t)op, wide, 5, tpb);
   g = std::max<uint64_t>(1, std::min<uint64_t>(g, map.size()));
   return hip_status(gzk::launch_batch((uint32_t)op, c->d_jobs, c->d_map, (uint32_t)map.size(),
                                       c->ctl(), tpb, (uint32_t)g, wide, st));
@@ -553,7 +553,7 @@ gz_status gz_plan_create(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t
   pl->tpb = tpb;
   for (const Job& J : jobs) pl->wide = pl->wide || J.dtype == GZ_F64;
   uint64_t g = (p && p->grid) ? p->grid
-                              : (uint64_t)c->cus * gzk::occupancy_blocks(3, pl->wide, 5, tpb);
+                              : (uint64_t)c->cus * gzk::occupancy_blocks(3 + (uint32_t)op, pl->wide, 5, tpb);
   pl->grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(g, map.size()));
   if (hipMalloc((void**)&pl->d_jobs, jobs.size() * sizeof(Job)) != hipSuccess ||
       hipMalloc((void**)&pl->d_map, map.size() * 4) != hipSuccess) {

@@ -16,7 +16,7 @@ hipError_t launch_batch(uint32_t op, const Job* d_jobs, const uint32_t* d_strip_
 hipError_t launch_quantize(const void* x, uint64_t n, const Job& J, int32_t* q, uint8_t* fail,
                            hipStream_t st);
 hipError_t launch_reset(const Ctl& C, hipStream_t st);
-// resident workgroups per CU of a kernel (op 3 = batched kernel; dtype sizes its LDS)
+// resident workgroups per CU of a kernel (op 3 + k = batched op k; dtype 1 = batch with fp64)
 int occupancy_blocks(uint32_t op, uint32_t dtype, uint32_t log2L, uint32_t tpb);
 
 }  // namespace gzk

@@ -353,6 +353,57 @@ __device__ __forceinline__ uint32_t plane_of(const uint32_t (&a)[32], uint32_t j
   return p;
 }
 
+// Where the lane's block sits in the incoming payload (dwords from the
+// payload start) and how it is coded; lets the fused step re-read a block.
+struct DecInfo {
+  uint32_t off_dw, kind, F;
+};
+
+// Rebuilds the lane's 32 values from its block's words at pw (LDS or global).
+template <typename T, int LPB, bool FULL>
+__device__ __forceinline__ void unpack_seg(const uint32_t* pw, uint32_t kind, uint32_t F,
+                                           uint32_t w, uint32_t vcnt, bool exists, T t,
+                                           T (&v)[32]) {
+  constexpr uint32_t EW = sizeof(T) / 4;
+  if (kind == K_RAW) {
+#pragma unroll
+    for (int i = 0; i < 32; ++i)
+      v[i] = (FULL || i < (int)vcnt) ? from_raw(pw + (w * 32 + i) * EW, T()) : (T)0;
+    return;
+  }
+  if (kind == K_ZERO || !exists) {
+#pragma unroll
+    for (int i = 0; i < 32; ++i) v[i] = (T)0;
+    return;
+  }
+  // L1D
+  const int32_t base = (int32_t)pw[0];
+  uint32_t a[32];
+#pragma unroll
+  for (int i = 0; i < 32; ++i) a[i] = 0;
+  uint32_t sg = 0;
+  if (F) {
+    sg = pw[1 + w];
+    for (uint32_t j = 0; j < F; ++j) {
+      const uint32_t p = pw[1 + (j + 1) * LPB + w];
+#pragma unroll
+      for (int i = 0; i < 32; ++i) a[i] |= ((p >> i) & 1u) << j;
+    }
+  }
+  uint32_t acc = 0;
+#pragma unroll
+  for (int i = 0; i < 32; ++i) {
+    const uint32_t neg = (uint32_t)__builtin_amdgcn_sbfe((int32_t)sg, i, 1);  // 0 or ~0
+    uint32_t d = (a[i] ^ neg) - neg;
+    if (i == 0 && w == 0) d = 0;
+    acc += d;
+    a[i] = acc;  // local prefix
+  }
+  const uint32_t carry = grp_excl_sum<LPB>(acc, w) + (uint32_t)base;
+#pragma unroll
+  for (int i = 0; i < 32; ++i) v[i] = (T)(int32_t)(carry + a[i]) * t;
+}
+
 // --------------------------------------------------------------- encode
 // Per-lane result of analysing a segment: the block's kind, width and size
 // (identical on the LPB lanes of a block) and this lane's share of the
@@ -644,9 +695,56 @@ __device__ __forceinline__ uint64_t seg_first(const Job& J, uint64_t seg) {
 
 // Scan, publish, stage, look back and write one strip (any mode).  KEEPV:
 // v stays valid for RAW blocks; otherwise RAW blocks re-read J.in.
-template <typename T, int L, int MODE, bool KEEPV>
+// Recomputes the fused step's sums y = x' + local of a lane (RAW blocks).
+struct FusedSrc {
+  const uint32_t* pay;  // incoming payload (global)
+  DecInfo di;
+  float t;
+  bool exists;
+};
+
+// Residual i of a lane read straight from its block's planes.
+template <int LPB>
+__device__ __forceinline__ uint32_t plane_res(const uint32_t* pw, uint32_t F, uint32_t sg,
+                                              uint32_t w, int i) {
+  uint32_t a = 0;
+  for (uint32_t j = 0; j < F; ++j) a |= ((pw[1 + (j + 1) * LPB + w] >> i) & 1u) << j;
+  const uint32_t neg = (uint32_t)__builtin_amdgcn_sbfe((int32_t)sg, i, 1);
+  return (i == 0 && w == 0) ? 0u : (a ^ neg) - neg;
+}
+
+// Stages the fused step's sums y = x' + local of a RAW block bit for bit,
+// re-deriving x' from the incoming block one element at a time (rare path,
+// kept rolled so it adds no register pressure).
+template <int LPB>
+__device__ __forceinline__ void fused_raw_stage(const Job& J, const FusedSrc& fs, uint64_t seg,
+                                             uint32_t w, uint32_t vcnt, uint32_t* st) {
+  const uint32_t* pw = fs.pay + fs.di.off_dw;
+  const uint32_t kind = fs.di.kind, F = fs.di.F;
+  uint32_t carry = 0, sg = 0;
+  if (kind == K_L1D) {
+    sg = F ? pw[1 + w] : 0u;
+    uint32_t tot = 0;
+    for (int i = 0; i < 32; ++i) tot += plane_res<LPB>(pw, F, sg, w, i);
+    carry = grp_excl_sum<LPB>(tot, w) + pw[0];
+  }
+  const float* loc = J.local + seg * SEG;
+  uint32_t acc = 0;
+  for (int i = 0; i < (int)vcnt; ++i) {
+    float xp = 0.0f;
+    if (kind == K_L1D) {
+      acc += plane_res<LPB>(pw, F, sg, w, i);
+      xp = (float)(int32_t)(carry + acc) * fs.t;
+    } else if (kind == K_RAW) {
+      xp = __uint_as_float(pw[w * 32 + i]);
+    }
+    st[w * 32 + i] = __float_as_uint(xp + loc[i]);
+  }
+}
+
+template <typename T, int L, int MODE, bool FUSED, bool FULL>
 __device__ void emit_strip(const Job& J, uint64_t s, uint64_t gs, const Ctl& C, Smem& sm,
-                           const T (&v)[32], uint32_t vcnt, const LaneCode& lc, bool skip) {
+                           uint32_t vcnt, const LaneCode& lc, const FusedSrc* fs, bool skip) {
   constexpr int LPB = L / 32;
   constexpr uint32_t EW = sizeof(T) / 4;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -674,13 +772,16 @@ __device__ void emit_strip(const Job& J, uint64_t s, uint64_t gs, const Ctl& C, 
       st[o + w] = lc.sg;
       for (uint32_t j = 0; j < F; ++j) st[o + (j + 1) * LPB + w] = plane_of(lc.a, j);
     }
-  } else if (kind == K_RAW) {
-    const T* src = (const T*)J.in + seg_first<MODE>(J, seg);
-#pragma unroll
-    for (int i = 0; i < 32; ++i) {
-      if (i < (int)vcnt) {
+  }
+  // a separate (not else) branch: the magnitudes are dead before it runs
+  if (kind == K_RAW) {
+    if (FUSED) {
+      fused_raw_stage<L / 32>(J, *fs, seg, w, vcnt, st);
+    } else {
+      const T* src = (const T*)J.in + seg_first<MODE>(J, seg);
+      for (int i = 0; i < (int)vcnt; ++i) {  // rolled: a rare path, kept small
         uint32_t wd[2];
-        raw_words(KEEPV ? v[i] : src[seg_off<MODE>(J, i)], wd);
+        raw_words(src[seg_off<MODE>(J, i)], wd);
         st[(w * 32 + i) * EW] = wd[0];
         if (EW == 2) st[(w * 32 + i) * EW + 1] = wd[1];
       }
@@ -750,15 +851,16 @@ __device__ void emit_strip(const Job& J, uint64_t s, uint64_t gs, const Ctl& C, 
   }
 }
 
-// Mode 0 strip encode (FULL: the strip lies entirely inside n).
-template <typename T, int L, bool FULL, bool KEEPV>
+// Mode 0 strip encode (FULL: the strip lies entirely inside n).  fs: the
+// fused step's incoming stream, to re-derive the sums of RAW blocks.
+template <typename T, int L, bool FULL, bool FUSED>
 __device__ __forceinline__ void encode_strip(const Job& J, uint64_t s, uint64_t gs, const Ctl& C,
                                              Smem& sm, const T (&v)[32], uint32_t vcnt,
-                                             bool skip) {
+                                             const FusedSrc* fs, bool skip) {
   const uint64_t seg = s * blockDim.x + threadIdx.x;
   LaneCode lc;
   analyze_1d<T, L, FULL>(J, seg, threadIdx.x & (L / 32 - 1), v, vcnt, lc);
-  emit_strip<T, L, 0, KEEPV>(J, s, gs, C, sm, v, vcnt, lc, skip);
+  emit_strip<T, L, 0, FUSED, FULL>(J, s, gs, C, sm, vcnt, lc, fs, skip);
 }
 
 // --------------------------------------------------------------- decode
@@ -851,7 +953,7 @@ __device__ __forceinline__ const uint32_t* copy_in(const uint32_t* src, uint32_t
 // returns false (and flags the context) if the strip is malformed.
 template <typename T, int L, bool FULL>
 __device__ bool decode_strip(const Job& J, const uint8_t* in, uint64_t in_bytes, uint64_t s,
-                             const Ctl& C, Smem& sm, T (&v)[32], uint32_t vcnt) {
+                             const Ctl& C, Smem& sm, T (&v)[32], uint32_t vcnt, DecInfo& di) {
   constexpr int LPB = L / 32;
   constexpr uint32_t EW = sizeof(T) / 4;
   const int tid = threadIdx.x;
@@ -910,45 +1012,10 @@ __device__ bool decode_strip(const Job& J, const uint8_t* in, uint64_t in_bytes,
     return false;
   }
 
-  const uint32_t* pw = S + boff;
-  const T t = step_of<T>(sm);
-  if (kind == K_RAW) {
-#pragma unroll
-    for (int i = 0; i < 32; ++i)
-      v[i] = (FULL || i < (int)vcnt) ? from_raw(pw + (w * 32 + i) * EW, T()) : (T)0;
-    return true;
-  }
-  if (kind == K_ZERO || !exists) {
-#pragma unroll
-    for (int i = 0; i < 32; ++i) v[i] = (T)0;
-    return true;
-  }
-  // L1D
-  const int32_t base = (int32_t)pw[0];
-  uint32_t a[32];
-#pragma unroll
-  for (int i = 0; i < 32; ++i) a[i] = 0;
-  uint32_t sg = 0;
-  if (F) {
-    sg = pw[1 + w];
-    for (uint32_t j = 0; j < F; ++j) {
-      const uint32_t p = pw[1 + (j + 1) * LPB + w];
-#pragma unroll
-      for (int i = 0; i < 32; ++i) a[i] |= ((p >> i) & 1u) << j;
-    }
-  }
-  uint32_t acc = 0;
-#pragma unroll
-  for (int i = 0; i < 32; ++i) {
-    const uint32_t neg = (uint32_t)__builtin_amdgcn_sbfe((int32_t)sg, i, 1);  // 0 or ~0
-    uint32_t d = (a[i] ^ neg) - neg;
-    if (i == 0 && w == 0) d = 0;
-    acc += d;
-    a[i] = acc;  // local prefix
-  }
-  const uint32_t carry = grp_excl_sum<LPB>(acc, w) + (uint32_t)base;
-#pragma unroll
-  for (int i = 0; i < 32; ++i) v[i] = (T)(int32_t)(carry + a[i]) * t;
+  di.off_dw = (uint32_t)E + boff;
+  di.kind = kind;
+  di.F = F;
+  unpack_seg<T, LPB, FULL>(S + boff, kind, F, w, vcnt, exists, step_of<T>(sm), v);
   return true;
 }
 
@@ -961,7 +1028,7 @@ __device__ __forceinline__ void compress_body(const Job& J, uint64_t s, uint64_t
   const uint32_t vcnt = FULL ? 32u : (e0 >= J.n ? 0u : (uint32_t)min((uint64_t)SEG, J.n - e0));
   T v[32];
   load_seg<T>((const T*)J.in + (vcnt ? e0 : 0), vcnt, v);
-  encode_strip<T, L, FULL, false>(J, s, gs, C, sm, v, vcnt, false);
+  encode_strip<T, L, FULL, false>(J, s, gs, C, sm, v, vcnt, nullptr, false);
 }
 
 template <typename T, int L>
@@ -980,7 +1047,8 @@ __device__ __forceinline__ void decompress_body(const Job& J, uint64_t s, const 
   const uint64_t e0 = (s * blockDim.x + threadIdx.x) * SEG;
   const uint32_t vcnt = FULL ? 32u : (e0 >= J.n ? 0u : (uint32_t)min((uint64_t)SEG, J.n - e0));
   T v[32];
-  if (decode_strip<T, L, FULL>(J, in, avail, s, C, sm, v, vcnt)) {
+  DecInfo di;
+  if (decode_strip<T, L, FULL>(J, in, avail, s, C, sm, v, vcnt, di)) {
     if (vcnt) store_seg<T>((T*)J.out + e0, vcnt, v);
   }
 }
@@ -997,14 +1065,18 @@ __device__ __forceinline__ void fused_body(const Job& J, uint64_t s, uint64_t gs
                                            Smem& sm) {
   const uint64_t e0 = (s * blockDim.x + threadIdx.x) * SEG;
   const uint32_t vcnt = FULL ? 32u : (e0 >= J.n ? 0u : (uint32_t)min((uint64_t)SEG, J.n - e0));
-  float a[32];
-  load_seg<float>(J.local + (vcnt ? e0 : 0), vcnt, a);  // in flight during the decode
   float v[32];
+  FusedSrc fs;
   const bool ok = decode_strip<float, L, FULL>(J, (const uint8_t*)J.in, J.in_bytes, s, C, sm,
-                                               v, vcnt);
+                                               v, vcnt, fs.di);
+  fs.pay = (const uint32_t*)((const uint8_t*)J.in + J.pay_off);
+  fs.t = sm.t32;
+  fs.exists = FULL || (s * blockDim.x + threadIdx.x) / (L / 32) < J.B;
+  float a[32];
+  load_seg<float>(J.local + (vcnt ? e0 : 0), vcnt, a);
 #pragma unroll
   for (int i = 0; i < 32; ++i) v[i] = v[i] + a[i];  // incoming + local, fp32
-  encode_strip<float, L, FULL, true>(J, s, gs, C, sm, v, vcnt, !ok);
+  encode_strip<float, L, FULL, true>(J, s, gs, C, sm, v, vcnt, &fs, !ok);
 }
 
 template <int L>
@@ -1031,6 +1103,8 @@ __device__ __forceinline__ void fused_one(const Job& J, uint64_t s, uint64_t gs,
   epilogue(C);
 
 #define GZ_KERNEL_ATTR __launch_bounds__(MAX_TPB) __attribute__((amdgpu_waves_per_eu(4, 8)))
+// decode + encode in one pass needs more registers than either alone
+#define GZ_FUSED_ATTR __launch_bounds__(MAX_TPB) __attribute__((amdgpu_waves_per_eu(3, 8)))
 
 template <typename T, int L>
 __global__ GZ_KERNEL_ATTR void k_compress(Job J, Ctl C) {
@@ -1043,42 +1117,57 @@ __global__ GZ_KERNEL_ATTR void k_decompress(Job J, Ctl C) {
 }
 
 template <int L>
-__global__ GZ_KERNEL_ATTR void k_fused(Job J, Ctl C) {
+__global__ GZ_FUSED_ATTR void k_fused(Job J, Ctl C) {
   GZ_STRIP_LOOP(J.nstrips, (fused_one<L>(J, t, t, C, sm)))
 }
 
-// Batched: strip_job maps a global strip to its job.
+// Batched: strip_job maps a global strip to its job.  One kernel per
+// operation; WIDE admits fp64 jobs (fp32-only batches avoid the register
+// pressure of the fp64 paths).
+template <uint32_t OP, bool WIDE>
 __device__ __forceinline__ void batch_body(const Job* __restrict__ jobs,
                                            const uint32_t* __restrict__ strip_job, uint32_t t,
-                                           uint32_t op, const Ctl& C, Smem& sm) {
+                                           const Ctl& C, Smem& sm) {
   const uint32_t j = strip_job[t];
   const Job J = jobs[j];
   const uint64_t s = t - J.strip0;
-  const uint32_t key = (op << 4) | (J.dtype << 3) | J.log2L;
-  switch (key) {
-    case (0u << 4) | (0u << 3) | 5u: compress_one<float, 32>(J, s, t, C, sm); break;
-    case (0u << 4) | (0u << 3) | 6u: compress_one<float, 64>(J, s, t, C, sm); break;
-    case (0u << 4) | (0u << 3) | 7u: compress_one<float, 128>(J, s, t, C, sm); break;
-    case (0u << 4) | (1u << 3) | 5u: compress_one<double, 32>(J, s, t, C, sm); break;
-    case (0u << 4) | (1u << 3) | 6u: compress_one<double, 64>(J, s, t, C, sm); break;
-    case (0u << 4) | (1u << 3) | 7u: compress_one<double, 128>(J, s, t, C, sm); break;
-    case (1u << 4) | (0u << 3) | 5u: decompress_one<float, 32>(J, s, C, sm); break;
-    case (1u << 4) | (0u << 3) | 6u: decompress_one<float, 64>(J, s, C, sm); break;
-    case (1u << 4) | (0u << 3) | 7u: decompress_one<float, 128>(J, s, C, sm); break;
-    case (1u << 4) | (1u << 3) | 5u: decompress_one<double, 32>(J, s, C, sm); break;
-    case (1u << 4) | (1u << 3) | 6u: decompress_one<double, 64>(J, s, C, sm); break;
-    case (1u << 4) | (1u << 3) | 7u: decompress_one<double, 128>(J, s, C, sm); break;
-    case (2u << 4) | (0u << 3) | 5u: fused_one<32>(J, s, t, C, sm); break;
-    case (2u << 4) | (0u << 3) | 6u: fused_one<64>(J, s, t, C, sm); break;
-    case (2u << 4) | (0u << 3) | 7u: fused_one<128>(J, s, t, C, sm); break;
-    default: break;
+  const uint32_t key = (J.dtype << 3) | J.log2L;
+  if (OP == 0) {
+    switch (key) {
+      case 5: compress_one<float, 32>(J, s, t, C, sm); break;
+      case 6: compress_one<float, 64>(J, s, t, C, sm); break;
+      case 7: compress_one<float, 128>(J, s, t, C, sm); break;
+      case 13: if (WIDE) compress_one<double, 32>(J, s, t, C, sm); break;
+      case 14: if (WIDE) compress_one<double, 64>(J, s, t, C, sm); break;
+      case 15: if (WIDE) compress_one<double, 128>(J, s, t, C, sm); break;
+      default: break;
+    }
+  } else if (OP == 1) {
+    switch (key) {
+      case 5: decompress_one<float, 32>(J, s, C, sm); break;
+      case 6: decompress_one<float, 64>(J, s, C, sm); break;
+      case 7: decompress_one<float, 128>(J, s, C, sm); break;
+      case 13: if (WIDE) decompress_one<double, 32>(J, s, C, sm); break;
+      case 14: if (WIDE) decompress_one<double, 64>(J, s, C, sm); break;
+      case 15: if (WIDE) decompress_one<double, 128>(J, s, C, sm); break;
+      default: break;
+    }
+  } else {
+    switch (key) {
+      case 5: fused_one<32>(J, s, t, C, sm); break;
+      case 6: fused_one<64>(J, s, t, C, sm); break;
+      case 7: fused_one<128>(J, s, t, C, sm); break;
+      default: break;
+    }
   }
 }
 
-__global__ GZ_KERNEL_ATTR void k_batch(const Job* __restrict__ jobs,
+template <uint32_t OP, bool WIDE>
+__global__ __launch_bounds__(MAX_TPB)
+__attribute__((amdgpu_waves_per_eu(OP == 2 ? 3 : 4, 8))) void k_batch(const Job* __restrict__ jobs,
                                        const uint32_t* __restrict__ strip_job, uint32_t total,
-                                       uint32_t op, Ctl C) {
-  GZ_STRIP_LOOP(total, (batch_body(jobs, strip_job, t, op, C, sm)))
+                                       Ctl C) {
+  GZ_STRIP_LOOP(total, (batch_body<OP, WIDE>(jobs, strip_job, t, C, sm)))
 }
 
 // Elementwise quantisation (verification entry point).
@@ -1161,12 +1250,37 @@ hipError_t launch_single(uint32_t op, const Job& J, const Ctl& C, uint32_t tpb, 
   return hipErrorInvalidValue;
 }
 
+static const void* batch_kernel(uint32_t op, bool wide) {
+  switch (op * 2 + (wide ? 1 : 0)) {
+    case 0: return (const void*)k_batch<0, false>;
+    case 1: return (const void*)k_batch<0, true>;
+    case 2: return (const void*)k_batch<1, false>;
+    case 3: return (const void*)k_batch<1, true>;
+    default: return (const void*)k_batch<2, false>;
+  }
+}
+
 hipError_t launch_batch(uint32_t op, const Job* d_jobs, const uint32_t* d_strip_job,
                         uint32_t total, const Ctl& C, uint32_t tpb, uint32_t grid, bool wide,
                         hipStream_t st) {
-  // batches holding fp64 jobs stage for the wider type
-  hipLaunchKernelGGL(k_batch, dim3(grid), dim3(tpb), stage_bytes(wide ? 1 : 0, tpb), st, d_jobs,
-                     d_strip_job, total, op, C);
+  const size_t lds = stage_bytes(wide ? 1 : 0, tpb);
+  if (op == 0 && !wide)
+    hipLaunchKernelGGL((k_batch<0, false>), dim3(grid), dim3(tpb), lds, st, d_jobs, d_strip_job,
+                       total, C);
+  else if (op == 0)
+    hipLaunchKernelGGL((k_batch<0, true>), dim3(grid), dim3(tpb), lds, st, d_jobs, d_strip_job,
+                       total, C);
+  else if (op == 1 && !wide)
+    hipLaunchKernelGGL((k_batch<1, false>), dim3(grid), dim3(tpb), lds, st, d_jobs, d_strip_job,
+                       total, C);
+  else if (op == 1)
+    hipLaunchKernelGGL((k_batch<1, true>), dim3(grid), dim3(tpb), lds, st, d_jobs, d_strip_job,
+                       total, C);
+  else if (op == 2)
+    hipLaunchKernelGGL((k_batch<2, false>), dim3(grid), dim3(tpb), lds, st, d_jobs, d_strip_job,
+                       total, C);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
@@ -1217,7 +1331,7 @@ int occupancy_blocks(uint32_t op, uint32_t dtype, uint32_t log2L, uint32_t tpb) 
       case 7: f = (const void*)k_fused<128>; break;
     }
   } else {
-    f = (const void*)k_batch;
+    f = batch_kernel(op - 3, dtype != 0);  // op 3/4/5: batched compress/decompress/fused
   }
   if (!f) return 1;
   const size_t lds = stage_bytes(op == 2 ? 0 : dtype, tpb);
