@@ -607,3 +607,34 @@ int gzo_scatter_compress(const void* root, int dtype, const uint64_t* counts,
   }
   return GZO_OK;
 }
+
+/* ------------------------------------------------------ selector data */
+/* Per 8x8 tile of an nx-wide fp32 field: its features, the sizes of its
+ * NONE, L1D and L2D encodings and the exhaustive-trial label (0 NONE,
+ * 1 L1D, 2 L2D; 255 when the tile is RAW or ZERO, whose features and sizes
+ * are then left as computed from q = 0 for failing elements). */
+int gzo_tile_trial(const float* x, uint64_t n, uint32_t nx, double eb, int8_t* feat,
+                   uint32_t* sizes, uint8_t* label) {
+  Geom g;
+  memset(&g, 0, sizeof g);
+  g.n = n; g.dtype = 0; g.L = 64; g.mode = 1; g.nx = nx; g.select = 1; g.eb = eb;
+  if (!check_params(&g, NULL) || !make_step(0, eb, &g.t32, &g.t64)) return GZO_EINVAL;
+  geom_fill(&g);
+  for (uint64_t b = 0; b < g.B; ++b) {
+    int32_t q[64];
+    int fail = 0, nonzero = 0;
+    for (int i = 0; i < 64; ++i) {
+      int32_t qi = 0;
+      fail |= quant_f32(x[elem_index(&g, b, i)], g.t32, eb, &qi);
+      q[i] = qi;
+      nonzero |= qi != 0;
+    }
+    gzo_tile_features(q, feat + 16 * b);
+    gzo_tile_sizes(q, sizes + 3 * b);
+    int best = 0;
+    for (int k = 1; k < 3; ++k)
+      if (sizes[3 * b + k] < sizes[3 * b + best]) best = k;
+    label[b] = (fail || !nonzero) ? 255 : (uint8_t)best;
+  }
+  return GZO_OK;
+}

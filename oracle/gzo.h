@@ -123,6 +123,9 @@ int gzo_mlp_forward(const uint8_t* blob, const int8_t* feat, int32_t* logits);
 uint64_t gzo_mlp_blob_bytes(void);
 /* Sizes in bytes of the NONE, L1D and L2D encodings of a tile. */
 void gzo_tile_sizes(const int32_t* q, uint32_t* sizes3);
+/* Features, sizes and exhaustive-trial labels of every tile of a field. */
+int gzo_tile_trial(const float* x, uint64_t n, uint32_t nx, double eb, int8_t* feat,
+                   uint32_t* sizes, uint8_t* label);
 
 #ifdef __cplusplus
 }

@@ -62,6 +62,7 @@ def lib():
         L.gzo_mlp_blob_bytes.restype = u64
         L.gzo_tile_sizes.argtypes = [vp, vp]
         L.gzo_tile_sizes.restype = None
+        L.gzo_tile_trial.argtypes = [vp, u64, u32, dbl, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -205,3 +206,16 @@ def tile_sizes(qtile):
     s = np.zeros(3, np.uint32)
     lib().gzo_tile_sizes(_ptr(q), _ptr(s))
     return s
+
+
+def tile_trial(x, nx, eb):
+    """(features int8[B,16], sizes uint32[B,3], labels uint8[B]) per tile."""
+    x = np.ascontiguousarray(x, dtype=np.float32).reshape(-1)
+    B = x.size // 64
+    f = np.zeros((B, 16), np.int8)
+    s = np.zeros((B, 3), np.uint32)
+    lab = np.zeros(B, np.uint8)
+    st = lib().gzo_tile_trial(_ptr(x), x.size, nx, eb, _ptr(f), _ptr(s), _ptr(lab))
+    if st:
+        raise OracleError(st, "tile_trial")
+    return f, s, lab

@@ -19,6 +19,7 @@
 
 #include "gz_common.h"
 #include "gz_kernels.h"
+#include "gz_select.h"
 #include "gzccl.h"
 
 using gzk::Ctl;
@@ -55,6 +56,7 @@ struct gz_ctx {
   int stage_next = 0;
   size_t stage_bytes = 0;
   Tuned tuned[3][2][3];  // [op][dtype][log2L-5]
+  float* train_ws = nullptr;  // selector training: per-sample backward terms
   Ctl ctl() const { return Ctl{ctrl, status, jobbase, blob}; }
 };
 
@@ -155,16 +157,26 @@ uint32_t pick_grid(const gz_ctx* c, uint32_t op, uint32_t dt, uint32_t L, uint32
   return (uint32_t)std::max<uint64_t>(g, 1);
 }
 
+uint32_t pick_tile_grid(const gz_ctx* c, uint32_t op, uint32_t tpb, uint64_t strips,
+                        const gz_params* p) {
+  uint64_t g = (p && p->grid) ? p->grid
+                              : (uint64_t)c->cus * gzk::occupancy_blocks(op, 0, 6, tpb);
+  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(g, strips));
+}
+
 bool params_ok(const gz_params* p, uint32_t& L) {
-  L = (p && p->block_len) ? p->block_len : 32;
+  L = (p && p->block_len) ? p->block_len : (p && p->mode == 1 ? 64 : 32);
   if (!valid_L(L)) return false;
   if (p) {
     if (p->threads != 0 && p->threads != 128 && p->threads != 256) return false;
-    if (p->mode != 0) return false;
-    if (p->nx != 0) return false;
+    if (p->mode > 1) return false;
+    if (p->mode == 0 && p->nx != 0) return false;
+    if (p->mode == 1 && (L != 64 || p->nx == 0 || p->nx % 8 != 0 || p->select > 2)) return false;
   }
   return true;
 }
+
+bool tile_mode(const gz_params* p) { return p && p->mode == 1; }
 
 gz_status hip_status(hipError_t e) { return e == hipSuccess ? GZ_OK : GZ_EHIP; }
 
@@ -277,6 +289,8 @@ gz_status gz_ctx_create(gz_ctx** out, int device, uint64_t max_elems, uint32_t m
   ok = ok && hipMalloc((void**)&c->blob, 1024) == hipSuccess;
   ok = ok && hipMalloc((void**)&c->d_jobs, (size_t)max_requests * sizeof(Job)) == hipSuccess;
   ok = ok && hipMalloc((void**)&c->d_map, c->max_strips * 4) == hipSuccess;
+  ok = ok && hipMalloc((void**)&c->train_ws,
+                       (size_t)gzs::MLP_MAX_BATCH * gzs::MLP_ROW * sizeof(float)) == hipSuccess;
   c->stage_bytes = (size_t)max_requests * sizeof(Job) + c->max_strips * 4;
   for (int k = 0; ok && k < STAGE_SLOTS; ++k) {
     ok = hipHostMalloc((void**)&c->stage[k], c->stage_bytes, hipHostMallocDefault) == hipSuccess &&
@@ -314,6 +328,7 @@ void gz_ctx_destroy(gz_ctx* c) {
   (void)hipFree(c->blob);
   (void)hipFree(c->d_jobs);
   (void)hipFree(c->d_map);
+  (void)hipFree(c->train_ws);
   delete c;
 }
 
@@ -367,6 +382,16 @@ gz_status gz_compress(gz_ctx* c, const void* d_in, uint64_t n, gz_dtype dtype, d
   J.in = d_in;
   J.out = d_out;
   J.out_bytes = (unsigned long long*)d_out_bytes;
+  if (tile_mode(p)) {
+    if (dtype != GZ_F32) return GZ_EUNSUPPORTED;
+    if (n % (8ull * p->nx) != 0) return GZ_EINVAL;
+    if (p->select == 0 && !c->blob_loaded) return GZ_EINVAL;
+    J.mode = 1;
+    J.nx = p->nx;
+    J.select = p->select;
+    const uint32_t grid = pick_tile_grid(c, 6, tpb, J.nstrips, p);
+    return hip_status(gzk::launch_tiles(0, J, c->ctl(), tpb, grid, (hipStream_t)stream));
+  }
   const uint32_t grid = pick_grid(c, 0, dtype, L, tpb, J.nstrips, p);
   return hip_status(gzk::launch_single(0, J, c->ctl(), tpb, grid, (hipStream_t)stream));
 }
@@ -387,6 +412,14 @@ gz_status gz_decompress(gz_ctx* c, const void* d_in, uint64_t in_bytes, uint64_t
   J.in = d_in;
   J.in_bytes = in_bytes;
   J.out = d_out;
+  if (tile_mode(p)) {
+    if (dtype != GZ_F32) return GZ_EUNSUPPORTED;
+    if (n % (8ull * p->nx) != 0) return GZ_EINVAL;
+    J.mode = 1;
+    J.nx = p->nx;
+    const uint32_t grid = pick_tile_grid(c, 7, tpb, J.nstrips, p);
+    return hip_status(gzk::launch_tiles(1, J, c->ctl(), tpb, grid, (hipStream_t)stream));
+  }
   const uint32_t grid = pick_grid(c, 1, dtype, L, tpb, J.nstrips, p);
   return hip_status(gzk::launch_single(1, J, c->ctl(), tpb, grid, (hipStream_t)stream));
 }
@@ -396,7 +429,7 @@ gz_status gz_fused_reduce_step(gz_ctx* c, const void* d_cmp_in, uint64_t in_byte
                                void* d_cmp_out, uint64_t out_cap, uint64_t* d_out_bytes,
                                gz_stream_t stream) {
   uint32_t L;
-  if (!c || !d_cmp_in || !d_cmp_out || !params_ok(p, L)) return GZ_EINVAL;
+  if (!c || !d_cmp_in || !d_cmp_out || !params_ok(p, L) || tile_mode(p)) return GZ_EINVAL;
   if (n && !d_local) return GZ_EINVAL;
   if (n * 4ull >= (1ull << 34)) return GZ_EINVAL;
   if (out_cap < bound_of(n, GZ_F32, L)) return GZ_ENOSPC;
@@ -426,7 +459,7 @@ gz_status gz_scatter_compress(gz_ctx* c, const void* d_root, gz_dtype dtype,
                               uint64_t* d_chunk_offsets, gz_stream_t stream) {
   uint32_t L;
   if (!c || !d_root || !d_out || !h_counts || !h_displs || !d_chunk_bytes || !d_chunk_offsets ||
-      (dtype != GZ_F32 && dtype != GZ_F64) || !params_ok(p, L) || nchunks == 0)
+      (dtype != GZ_F32 && dtype != GZ_F64) || !params_ok(p, L) || tile_mode(p) || nchunks == 0)
     return GZ_EINVAL;
   if (nchunks > c->max_jobs) return GZ_ENOSPC;
   const uint32_t tpb = pick_tpb(c, 0, dtype, L, p);
@@ -478,7 +511,7 @@ gz_status gz_scatter_decompress(gz_ctx* c, const void* d_packed, uint64_t packed
                                 gz_stream_t stream) {
   uint32_t L;
   if (!c || !d_packed || !d_chunk_offsets || !h_counts || !h_displs || !d_root ||
-      (dtype != GZ_F32 && dtype != GZ_F64) || !params_ok(p, L) || nchunks == 0)
+      (dtype != GZ_F32 && dtype != GZ_F64) || !params_ok(p, L) || tile_mode(p) || nchunks == 0)
     return GZ_EINVAL;
   if (nchunks > c->max_jobs) return GZ_ENOSPC;
   const uint32_t tpb = pick_tpb(c, 1, dtype, L, p);
@@ -626,21 +659,188 @@ void gz_graph_destroy(gz_graph* g) {
 
 }  // extern "C"
 
+
 extern "C" {
-gz_status gz_tune(gz_ctx*, gz_dtype, uint32_t, uint64_t, const char*, gz_params*) {
-  return GZ_EUNSUPPORTED;
+
+// ---- autotuner: launch shapes (threads, grid) and optionally block length.
+// Shapes never change the bytes; block length does (it is recorded in the
+// stream), so tuning it is opt-in (block_len == 0).
+static bool cache_lookup(const char* path, const std::string& key, uint32_t& tpb,
+                         uint32_t& grid) {
+  if (!path) return false;
+  FILE* f = fopen(path, "r");
+  if (!f) return false;
+  char line[512];
+  bool hit = false;
+  while (fgets(line, sizeof line, f)) {
+    char k[256];
+    unsigned t, g;
+    if (sscanf(line, " {\"key\": \"%255[^\"]\", \"tpb\": %u, \"grid\": %u", k, &t, &g) == 3 &&
+        key == k) {
+      tpb = t;
+      grid = g;
+      hit = true;
+    }
+  }
+  fclose(f);
+  return hit;
 }
-gz_status gz_selector_load(gz_ctx*, const void*, uint64_t) { return GZ_EUNSUPPORTED; }
-gz_status gz_tile_trial(gz_ctx*, const float*, uint64_t, uint32_t, double, int8_t*, uint32_t*,
-                        uint8_t*, gz_stream_t) {
-  return GZ_EUNSUPPORTED;
+
+static void cache_store(const char* path, const std::string& key, uint32_t tpb, uint32_t grid,
+                        float ms) {
+  if (!path) return;
+  FILE* f = fopen(path, "a");
+  if (!f) return;
+  fprintf(f, "{\"key\": \"%s\", \"tpb\": %u, \"grid\": %u, \"ms\": %.4f}\n", key.c_str(),
+          tpb, grid, ms);
+  fclose(f);
 }
-gz_status gz_mlp_grad(gz_ctx*, const float*, const int8_t*, const uint8_t*, uint64_t, float*,
-                      float*, gz_stream_t) {
-  return GZ_EUNSUPPORTED;
+
+static gz_status time_op(gz_ctx* c, uint32_t op, void* x, void* s, uint64_t cap,
+                         unsigned long long* nb, uint64_t n, gz_dtype dt, uint32_t L,
+                         uint32_t tpb, uint32_t grid, hipStream_t st, hipEvent_t e0,
+                         hipEvent_t e1, float& ms) {
+  gz_params p = {L, tpb, grid, 0, 0, 0};
+  auto run = [&]() -> gz_status {
+    return op == 0 ? gz_compress(c, x, n, dt, 1e-3, &p, s, cap, (uint64_t*)nb, st)
+                   : gz_decompress(c, s, cap, n, dt, &p, x, st);
+  };
+  gz_status r = run();
+  if (r != GZ_OK) return r;
+  if (hipEventRecord(e0, st) != hipSuccess) return GZ_EHIP;
+  for (int k = 0; k < 3 && r == GZ_OK; ++k) r = run();
+  if (r != GZ_OK) return r;
+  if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+    return GZ_EHIP;
+  if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return GZ_EHIP;
+  ms /= 3;
+  return GZ_OK;
 }
-gz_status gz_mlp_adam(gz_ctx*, float*, const float*, float*, float*, uint32_t, float,
-                      gz_stream_t) {
-  return GZ_EUNSUPPORTED;
+
+gz_status gz_tune(gz_ctx* c, gz_dtype dt, uint32_t block_len, uint64_t n, const char* cache_path,
+                  gz_params* best) {
+  if (!c || (dt != GZ_F32 && dt != GZ_F64) || n == 0 || n > c->max_elems) return GZ_EINVAL;
+  if (block_len != 0 && !valid_L(block_len)) return GZ_EINVAL;
+  const uint32_t Ls[3] = {32, 64, 128};
+  const uint64_t cap = bound_of(n, dt, 32);  // the largest bound of the three
+  void *x = nullptr, *s = nullptr;
+  unsigned long long* nb = nullptr;
+  hipStream_t st = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  gz_status r = GZ_OK;
+  if (hipMalloc(&x, n * esize(dt)) != hipSuccess || hipMalloc(&s, cap) != hipSuccess ||
+      hipMalloc((void**)&nb, 8) != hipSuccess ||
+      hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    r = GZ_ENOMEM;
+  if (r == GZ_OK) r = hip_status(gzk::launch_fill(x, n, dt, st));
+  float best_total = 1e30f;
+  uint32_t best_L = block_len ? block_len : 32;
+  for (int li = 0; r == GZ_OK && li < 3; ++li) {
+    const uint32_t L = Ls[li];
+    if (block_len && L != block_len) continue;
+    float total = 0;
+    for (uint32_t op = 0; r == GZ_OK && op < 2; ++op) {
+      char keyb[128];
+      snprintf(keyb, sizeof keyb, "gfx950/cus%d/op%u/dt%u/L%u/n%llu", c->cus, op, (unsigned)dt,
+               L, (unsigned long long)n);
+      uint32_t tpb = 0, grid = 0;
+      float ms = 0;
+      if (cache_lookup(cache_path, keyb, tpb, grid)) {
+        r = time_op(c, op, x, s, cap, nb, n, dt, L, tpb, grid, st, e0, e1, ms);
+      } else {
+        float bms = 1e30f;
+        const uint32_t tpbs[2] = {128, 256};
+        for (uint32_t ti = 0; r == GZ_OK && ti < 2; ++ti) {
+          const int occ = gzk::occupancy_blocks(op, dt, log2_of(L), tpbs[ti]);
+          const uint32_t grids[4] = {(uint32_t)c->cus, 2u * c->cus, (uint32_t)(c->cus * occ),
+                                     (uint32_t)(c->cus * occ * 2)};
+          for (uint32_t gi = 0; r == GZ_OK && gi < 4; ++gi) {
+            float t = 0;
+            r = time_op(c, op, x, s, cap, nb, n, dt, L, tpbs[ti], grids[gi], st, e0, e1, t);
+            if (r == GZ_OK && t < bms) {
+              bms = t;
+              tpb = tpbs[ti];
+              grid = grids[gi];
+            }
+          }
+        }
+        ms = bms;
+        if (r == GZ_OK) cache_store(cache_path, keyb, tpb, grid, ms);
+      }
+      if (r == GZ_OK) {
+        c->tuned[op][dt][log2_of(L) - 5].tpb = tpb;
+        c->tuned[op][dt][log2_of(L) - 5].grid = grid;
+        total += ms;
+      }
+    }
+    if (r == GZ_OK && total < best_total) {
+      best_total = total;
+      best_L = L;
+    }
+  }
+  if (r == GZ_OK && hipStreamSynchronize(st) != hipSuccess) r = GZ_EHIP;
+  if (r == GZ_OK && best) {
+    const Tuned& t = c->tuned[0][dt][log2_of(best_L) - 5];
+    *best = gz_params{best_L, t.tpb, t.grid, 0, 0, 0};
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (st) (void)hipStreamDestroy(st);
+  (void)hipFree(x);
+  (void)hipFree(s);
+  (void)hipFree(nb);
+  return r;
 }
+
+gz_status gz_selector_load(gz_ctx* c, const void* h_blob, uint64_t bytes) {
+  if (!c || !h_blob || bytes != 756) return GZ_EINVAL;
+  const uint8_t* b = (const uint8_t*)h_blob;
+  uint32_t magic, shift;
+  memcpy(&magic, b, 4);
+  memcpy(&shift, b + 4, 4);
+  if (magic != 0x314D5A47u || shift > 24) return GZ_EINVAL;
+  for (int k = 0; k < 35; ++k) {  // b1[32] at 520, b2[3] at 744
+    int32_t v;
+    memcpy(&v, b + (k < 32 ? 520 + 4 * k : 744 + 4 * (k - 32)), 4);
+    if (v <= -(1 << 24) || v >= (1 << 24)) return GZ_EINVAL;
+  }
+  if (hipMemcpy(c->blob, h_blob, bytes, hipMemcpyHostToDevice) != hipSuccess) return GZ_EHIP;
+  c->blob_loaded = true;
+  return GZ_OK;
 }
+
+gz_status gz_tile_trial(gz_ctx* c, const float* d_in, uint64_t n, uint32_t nx, double eb,
+                        int8_t* d_feat, uint32_t* d_sizes, uint8_t* d_label, gz_stream_t stream) {
+  if (!c || nx == 0 || nx % 8 != 0 || n % (8ull * nx) != 0) return GZ_EINVAL;
+  if (n && (!d_in || !d_feat || !d_sizes || !d_label)) return GZ_EINVAL;
+  Job J;
+  memset(&J, 0, sizeof J);
+  J.dtype = GZ_F32;
+  if (!set_bound(J, GZ_F32, eb)) return GZ_EINVAL;
+  if (!n) return GZ_OK;
+  J.n = n;
+  J.B = n / 64;
+  J.nx = nx;
+  J.mode = 1;
+  return hip_status(gzk::launch_tile_trial(J, d_feat, d_sizes, d_label, (hipStream_t)stream));
+}
+
+gz_status gz_mlp_grad(gz_ctx* c, const float* d_w, const int8_t* d_feat, const uint8_t* d_label,
+                      uint64_t nsamp, float* d_grad, float* d_loss, gz_stream_t stream) {
+  if (!c || !d_w || !d_grad || !d_loss || nsamp > gzs::MLP_MAX_BATCH) return GZ_EINVAL;
+  if (nsamp && (!d_feat || !d_label)) return GZ_EINVAL;
+  return hip_status(gzs::launch_mlp_grad(d_w, d_feat, d_label, (uint32_t)nsamp, c->train_ws,
+                                         d_grad, d_loss, (hipStream_t)stream));
+}
+
+gz_status gz_mlp_adam(gz_ctx* c, float* d_w, const float* d_grad, float* d_m, float* d_v,
+                      uint32_t step, float lr, gz_stream_t stream) {
+  if (!c || !d_w || !d_grad || !d_m || !d_v || step == 0 || !(lr > 0.0f)) return GZ_EINVAL;
+  const float bc1 = (float)(1.0 - pow(0.9, (double)step));
+  const float bc2 = (float)(1.0 - pow(0.999, (double)step));
+  return hip_status(gzs::launch_mlp_adam(d_w, d_grad, d_m, d_v, lr, bc1, bc2,
+                                         (hipStream_t)stream));
+}
+
+}  // extern "C"

@@ -15,8 +15,15 @@ hipError_t launch_batch(uint32_t op, const Job* d_jobs, const uint32_t* d_strip_
                         hipStream_t st);
 hipError_t launch_quantize(const void* x, uint64_t n, const Job& J, int32_t* q, uint8_t* fail,
                            hipStream_t st);
+// mode 1 (8x8 tiles, fp32): op 0 compress, 1 decompress
+hipError_t launch_tiles(uint32_t op, const Job& J, const Ctl& C, uint32_t tpb, uint32_t grid,
+                        hipStream_t st);
+hipError_t launch_tile_trial(const Job& J, int8_t* feat, uint32_t* sizes, uint8_t* label,
+                             hipStream_t st);
+hipError_t launch_fill(void* x, uint64_t n, uint32_t dtype, hipStream_t st);  // tuning input
 hipError_t launch_reset(const Ctl& C, hipStream_t st);
-// resident workgroups per CU of a kernel (op 3 + k = batched op k; dtype 1 = batch with fp64)
+// resident workgroups per CU of a kernel (op 3 + k = batched op k, dtype 1 = batch with
+// fp64; op 6/7 = tile compress/decompress)
 int occupancy_blocks(uint32_t op, uint32_t dtype, uint32_t log2L, uint32_t tpb);
 
 }  // namespace gzk

@@ -229,6 +229,7 @@ struct Smem {
   float t32;                     // decode: step of the incoming stream
   double t64;
   uint32_t hb[MAX_TPB / 4];      // header bytes of the strip's blocks
+  uint32_t wts[192];             // selector weights (tile mode)
 };
 
 // Staging buffer for one strip's payload (dynamic LDS): 16 bytes of headroom
@@ -949,9 +950,87 @@ __device__ __forceinline__ const uint32_t* copy_in(const uint32_t* src, uint32_t
   return g_stage + delta;
 }
 
+// Rebuilds the lane's 4 tile rows (mode 1) from its block's words at pw.
+// Each lane first sums its own rows as if the row above were zero; lane 1
+// then adds lane 0's last row (L2D) or its first-column value (L1D).
+template <typename T>
+__device__ __forceinline__ void unpack_tile(const uint32_t* pw, uint32_t kind, uint32_t F,
+                                            uint32_t w, bool exists, T t, T (&v)[32]) {
+  if (kind == K_RAW) {
+#pragma unroll
+    for (int i = 0; i < 32; ++i) v[i] = from_raw(pw + (w * 32 + i) * (sizeof(T) / 4), T());
+    return;
+  }
+  if (kind == K_ZERO || !exists) {
+#pragma unroll
+    for (int i = 0; i < 32; ++i) v[i] = (T)0;
+    return;
+  }
+  const uint32_t o = kind == K_NONE ? 0u : 1u;
+  const uint32_t base = o ? pw[0] : 0u;
+  uint32_t q[32];
+#pragma unroll
+  for (int i = 0; i < 32; ++i) q[i] = 0;
+  uint32_t sg = 0;
+  if (F) {
+    sg = pw[o + w];
+    for (uint32_t j = 0; j < F; ++j) {
+      const uint32_t p = pw[o + (j + 1) * 2 + w];
+#pragma unroll
+      for (int i = 0; i < 32; ++i) q[i] |= ((p >> i) & 1u) << j;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 32; ++i) {  // signed residuals
+    const uint32_t neg = (uint32_t)__builtin_amdgcn_sbfe((int32_t)sg, i, 1);
+    q[i] = (q[i] ^ neg) - neg;
+  }
+  if (kind == K_L1D) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int i = 8 * r + c;
+        if (c) q[i] = q[i - 1] + q[i];
+        else if (r) q[i] = q[i - 8] + q[i];
+        else q[i] = w == 0 ? base : q[i];  // (0,0) holds the base
+      }
+    }
+    const uint32_t carry = __shfl_up(q[24], 1);  // lane 0's q(3,0)
+    if (w) {
+#pragma unroll
+      for (int i = 0; i < 32; ++i) q[i] += carry;
+    }
+  } else if (kind == K_L2D) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      uint32_t acc = 0;  // v(r,c): the row prefix of d
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int i = 8 * r + c;
+        if (r == 0 && w == 0) {
+          q[i] = c ? q[i - 1] + q[i] : base;  // first row: L1D along the row
+        } else {
+          acc += q[i];
+          q[i] = (r ? q[i - 8] : 0u) + acc;
+        }
+      }
+    }
+    uint32_t up[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) up[c] = __shfl_up(q[24 + c], 1);  // lane 0's row 3
+    if (w) {
+#pragma unroll
+      for (int i = 0; i < 32; ++i) q[i] += up[i % 8];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 32; ++i) v[i] = (T)(int32_t)q[i] * t;
+}
+
 // Decodes the lane's segment of strip s of the stream at `in` into v[];
 // returns false (and flags the context) if the strip is malformed.
-template <typename T, int L, bool FULL>
+template <typename T, int L, bool FULL, int MODE = 0>
 __device__ bool decode_strip(const Job& J, const uint8_t* in, uint64_t in_bytes, uint64_t s,
                              const Ctl& C, Smem& sm, T (&v)[32], uint32_t vcnt, DecInfo& di) {
   constexpr int LPB = L / 32;
@@ -989,7 +1068,8 @@ __device__ bool decode_strip(const Job& J, const uint8_t* in, uint64_t in_bytes,
   bool hv = true;
   if (kind == K_ZERO) hv = F == 0;
   else if (kind == K_RAW) { hv = F == 0; size_dw = m * EW; }
-  else if (kind == K_L1D) size_dw = 1u + (F ? (F + 1u) * LPB : 0u);
+  else if (kind == K_L1D || (MODE == 1 && kind == K_L2D)) size_dw = 1u + (F ? (F + 1u) * LPB : 0u);
+  else if (MODE == 1 && kind == K_NONE) { hv = F > 0; size_dw = (F + 1u) * LPB; }
   else hv = false;
   if (!hv) size_dw = 0;
 
@@ -1015,7 +1095,8 @@ __device__ bool decode_strip(const Job& J, const uint8_t* in, uint64_t in_bytes,
   di.off_dw = (uint32_t)E + boff;
   di.kind = kind;
   di.F = F;
-  unpack_seg<T, LPB, FULL>(S + boff, kind, F, w, vcnt, exists, step_of<T>(sm), v);
+  if (MODE == 0) unpack_seg<T, LPB, FULL>(S + boff, kind, F, w, vcnt, exists, step_of<T>(sm), v);
+  else unpack_tile<T>(S + boff, kind, F, w, exists, step_of<T>(sm), v);
   return true;
 }
 
@@ -1170,6 +1251,133 @@ __attribute__((amdgpu_waves_per_eu(OP == 2 ? 3 : 4, 8))) void k_batch(const Job*
   GZ_STRIP_LOOP(total, (batch_body<OP, WIDE>(jobs, strip_job, t, C, sm)))
 }
 
+// ------------------------------------------------------------ tile mode
+// Mode 1 (fp32, 8x8 tiles, L = 64): lane w of tile seg/2 owns its rows
+// 4w..4w+3, loaded/stored as 4 rows of 8 floats.
+__device__ __forceinline__ void load_tile(const Job& J, const float* __restrict__ p, bool ex,
+                                          float (&v)[32]) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      f4u t = ex ? *(const f4u*)(p + r * (uint64_t)J.nx + 4 * h) : f4u{0, 0, 0, 0};
+      v[8 * r + 4 * h] = t.x; v[8 * r + 4 * h + 1] = t.y;
+      v[8 * r + 4 * h + 2] = t.z; v[8 * r + 4 * h + 3] = t.w;
+    }
+  }
+}
+__device__ __forceinline__ void store_tile(const Job& J, float* __restrict__ p,
+                                           const float (&v)[32]) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      f4u t;
+      t.x = v[8 * r + 4 * h]; t.y = v[8 * r + 4 * h + 1];
+      t.z = v[8 * r + 4 * h + 2]; t.w = v[8 * r + 4 * h + 3];
+      *(f4u*)(p + r * (uint64_t)J.nx + 4 * h) = t;
+    }
+  }
+}
+
+template <bool FULL>
+__device__ __forceinline__ void compress_tiles_body(const Job& J, uint64_t s, uint64_t gs,
+                                                    const Ctl& C, Smem& sm) {
+  const uint64_t seg = s * blockDim.x + threadIdx.x;
+  const bool ex = FULL || (seg >> 1) < J.B;
+  float v[32];
+  load_tile(J, (const float*)J.in + (ex ? seg_first<1>(J, seg) : 0), ex, v);
+  LaneCode lc;
+  analyze_tile(J, threadIdx.x & 1u, v, ex, sm.wts, lc);
+  emit_strip<float, 64, 1, false, FULL>(J, s, gs, C, sm, ex ? 32u : 0u, lc, nullptr, false);
+}
+
+__device__ __forceinline__ void load_weights(const Ctl& C, Smem& sm) {
+  for (uint32_t k = threadIdx.x; k < 189; k += blockDim.x) sm.wts[k] = ((const uint32_t*)C.blob)[k];
+  __syncthreads();
+}
+
+__global__ GZ_FUSED_ATTR void k_compress_tiles(Job J, Ctl C) {
+  __shared__ Smem sm;
+  load_weights(C, sm);
+  uint32_t t = first_ticket(C, sm);
+  while (t < J.nstrips) {
+    uint32_t nxt = 0;
+    if (threadIdx.x == 0) nxt = atomicAdd(&C.ctrl->ticket, 1u);
+    if ((t + 1) * (uint64_t)blockDim.x <= 2 * J.B) compress_tiles_body<true>(J, t, t, C, sm);
+    else compress_tiles_body<false>(J, t, t, C, sm);
+    __syncthreads();
+    if (threadIdx.x == 0) sm.cur = nxt;
+    __syncthreads();
+    t = sm.cur;
+  }
+  epilogue(C);
+}
+
+__global__ GZ_KERNEL_ATTR void k_decompress_tiles(Job J, Ctl C) {
+  __shared__ Smem sm;
+  uint32_t t = first_ticket(C, sm);
+  while (t < J.nstrips) {
+    uint32_t nxt = 0;
+    if (threadIdx.x == 0) nxt = atomicAdd(&C.ctrl->ticket, 1u);
+    const uint64_t seg = t * (uint64_t)blockDim.x + threadIdx.x;
+    const bool ex = (seg >> 1) < J.B;
+    float v[32];
+    DecInfo di;
+    if (decode_strip<float, 64, false, 1>(J, (const uint8_t*)J.in, J.in_bytes, t, C, sm, v,
+                                          ex ? 32u : 0u, di) && ex)
+      store_tile(J, (float*)J.out + seg_first<1>(J, seg), v);
+    __syncthreads();
+    if (threadIdx.x == 0) sm.cur = nxt;
+    __syncthreads();
+    t = sm.cur;
+  }
+  epilogue(C);
+}
+
+// Training data of the selector: per tile the 16 features, the sizes of the
+// three encodings and the exhaustive-trial label (255: RAW or ZERO tile).
+__global__ __launch_bounds__(256) void k_tile_trial(Job J, int8_t* __restrict__ feat,
+                                                   uint32_t* __restrict__ sizes,
+                                                   uint8_t* __restrict__ label) {
+  const uint64_t nseg = 2 * J.B;
+  for (uint64_t seg = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+       seg - threadIdx.x < nseg; seg += (uint64_t)gridDim.x * blockDim.x) {
+    // whole waves iterate together (the tile's two lanes shuffle)
+    const bool ex = seg < nseg;
+    const uint32_t w = threadIdx.x & 1u;
+    float v[32];
+    load_tile(J, (const float*)J.in + (ex ? seg_first<1>(J, seg) : 0), ex, v);
+    int32_t q[32];
+    bool bad;
+    tile_quant(J, v, q, bad);
+    int32_t up[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) up[c] = __shfl_up(q[24 + c], 1);
+    uint32_t f[4];
+    tile_features(q, w, f);
+    const uint32_t o0 = tile_or<0>(q, up, w), o1 = tile_or<1>(q, up, w), o2 = tile_or<2>(q, up, w);
+    const uint32_t s0 = size_of(K_NONE, o0 ? 32u - __clz(o0) : 0u);
+    const uint32_t s1 = size_of(K_L1D, o1 ? 32u - __clz(o1) : 0u);
+    const uint32_t s2 = size_of(K_L2D, o2 ? 32u - __clz(o2) : 0u);
+    uint32_t best = 0, bs = s0;
+    if (s1 < bs) { best = 1; bs = s1; }
+    if (s2 < bs) best = 2;
+    const bool zero = (grp_or<2>(q[0] != 0 ? 1u : 0u) | o0) == 0;
+    if (ex && w == 0) {
+      const uint64_t b = seg >> 1;
+      ((uint32_t*)feat)[4 * b + 0] = f[0];
+      ((uint32_t*)feat)[4 * b + 1] = f[1];
+      ((uint32_t*)feat)[4 * b + 2] = f[2];
+      ((uint32_t*)feat)[4 * b + 3] = f[3];
+      sizes[3 * b + 0] = 4 * s0;
+      sizes[3 * b + 1] = 4 * s1;
+      sizes[3 * b + 2] = 4 * s2;
+      label[b] = (bad || zero) ? 255 : (uint8_t)best;
+    }
+  }
+}
+
 // Elementwise quantisation (verification entry point).
 template <typename T>
 __global__ void k_quantize(const T* __restrict__ x, uint64_t n, Job J, int32_t* __restrict__ q,
@@ -1180,6 +1388,21 @@ __global__ void k_quantize(const T* __restrict__ x, uint64_t n, Job J, int32_t* 
     int32_t qi = quant_t<T>(x[i], J, bad);
     q[i] = bad ? 0 : qi;
     fail[i] = bad ? 1 : 0;
+  }
+}
+
+// Smooth synthetic signal with hashed noise (autotuning input).
+template <typename T>
+__global__ void k_fill(T* __restrict__ x, uint64_t n) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x) {
+    const float u = (float)(i % 1048576) * (1.0f / 1048576.0f);
+    uint32_t h = (uint32_t)i * 2654435761u;
+    h ^= h >> 15;
+    h *= 2246822519u;
+    h ^= h >> 13;
+    const float noise = ((float)(h & 0xFFFFu) - 32768.0f) * (1.0e-3f / 32768.0f);
+    x[i] = (T)(sinf(6.2831853f * 7.0f * u) + 0.5f * sinf(6.2831853f * 31.0f * u) + noise);
   }
 }
 
@@ -1297,6 +1520,31 @@ hipError_t launch_quantize(const void* x, uint64_t n, const Job& J, int32_t* q, 
   return hipGetLastError();
 }
 
+hipError_t launch_tiles(uint32_t op, const Job& J, const Ctl& C, uint32_t tpb, uint32_t grid,
+                        hipStream_t st) {
+  if (op == 0)
+    hipLaunchKernelGGL(k_compress_tiles, dim3(grid), dim3(tpb), stage_bytes(0, tpb), st, J, C);
+  else
+    hipLaunchKernelGGL(k_decompress_tiles, dim3(grid), dim3(tpb), stage_bytes(0, tpb), st, J, C);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_trial(const Job& J, int8_t* feat, uint32_t* sizes, uint8_t* label,
+                             hipStream_t st) {
+  const uint64_t segs = 2 * J.B;
+  uint64_t blocks = (segs + 255) / 256;
+  const uint32_t grid = (uint32_t)(blocks < 8192 ? (blocks ? blocks : 1) : 8192);
+  hipLaunchKernelGGL(k_tile_trial, dim3(grid), dim3(256), 0, st, J, feat, sizes, label);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(void* x, uint64_t n, uint32_t dtype, hipStream_t st) {
+  const uint32_t grid = 4096;
+  if (dtype == 0) hipLaunchKernelGGL(k_fill<float>, dim3(grid), dim3(256), 0, st, (float*)x, n);
+  else hipLaunchKernelGGL(k_fill<double>, dim3(grid), dim3(256), 0, st, (double*)x, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_reset(const Ctl& C, hipStream_t st) {
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, st, C);
   return hipGetLastError();
@@ -1330,11 +1578,15 @@ int occupancy_blocks(uint32_t op, uint32_t dtype, uint32_t log2L, uint32_t tpb) 
       case 6: f = (const void*)k_fused<64>; break;
       case 7: f = (const void*)k_fused<128>; break;
     }
+  } else if (op == 6) {
+    f = (const void*)k_compress_tiles;
+  } else if (op == 7) {
+    f = (const void*)k_decompress_tiles;
   } else {
     f = batch_kernel(op - 3, dtype != 0);  // op 3/4/5: batched compress/decompress/fused
   }
   if (!f) return 1;
-  const size_t lds = stage_bytes(op == 2 ? 0 : dtype, tpb);
+  const size_t lds = stage_bytes(op == 2 || op >= 6 ? 0 : dtype, tpb);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, (int)tpb, lds) != hipSuccess || nb < 1)
     nb = 1;
   return nb;

@@ -152,3 +152,23 @@ def request_data(req):
         base = g.uniform(100.0, 200.0) + g.uniform(-0.05, 0.05) * np.arange(n)
         x = (base + g.poisson(50.0, n)) / 100.0
     return x.astype(req["dtype"])
+
+
+def selector_fields(seed=0, grf_shape=(64, 256, 256), n_images=2, image_hw=(1024, 1024),
+                    sparse_n=1 << 22):
+    """Mixed fields for the predictor selector, as (array float32, nx, eb):
+    a smooth 3D GRF viewed as rows of its last axis, noisy images (the frame
+    generator) and a 50%-zero sparse array tiled as 8-wide rows; each with
+    eb = 1e-4 x its value range."""
+    out = []
+    g = grf(grf_shape, seed=seed).reshape(-1)
+    out.append(g)
+    for k in range(n_images):
+        out.append(frames(1, image_hw[0], image_hw[1], seed=seed * 7919 + k + 1).reshape(-1))
+    out.append(sparse(sparse_n, seed=seed * 7919 + 97))
+    nxs = [grf_shape[-1]] + [image_hw[1]] * n_images + [8]
+    res = []
+    for x, nx in zip(out, nxs):
+        rng_ = float(x.max()) - float(x.min())
+        res.append((x.astype(np.float32), nx, 1e-4 * (rng_ if rng_ > 0 else 1.0)))
+    return res

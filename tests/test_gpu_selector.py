@@ -1,0 +1,153 @@
+"""GPU parity of the tile mode (8x8 tiles, NONE/L1D/L2D), the tile-trial
+kernel and the selector's training gradients against the CPU oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import mlp
+from paper_2308_05199_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gz():
+    import torch
+    from paper_2308_05199_amd import gzccl
+    assert torch.cuda.is_available()
+    return gzccl
+
+
+@pytest.fixture(scope="module")
+def ctx(gz):
+    c = gz.Context(0, max_elems=1 << 26, max_requests=64)
+    yield c
+    c.close()
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def fields():
+    return synth.selector_fields(5, grf_shape=(8, 128, 128), n_images=1, image_hw=(256, 512),
+                                 sparse_n=1 << 16)
+
+
+def tile_params(gz, nx, select, threads=0):
+    import ctypes
+    return gz.gz_params(64, threads, 0, 1, select, nx)
+
+
+def gpu_tile_stream(gz, ctx, x, nx, eb, select, threads=0):
+    import ctypes
+    import torch
+    xs = dev(x)
+    cap = gz.bound(x.size, gz.GZ_F32, 64)
+    out = torch.empty(cap, dtype=torch.uint8, device="cuda")
+    nb = torch.zeros(1, dtype=torch.int64, device="cuda")
+    p = tile_params(gz, nx, select, threads)
+    gz.check(gz.gz_compress(ctx.h, gz._ptr(xs), x.size, gz.GZ_F32, eb, ctypes.byref(p),
+                            gz._ptr(out), cap, gz._ptr(nb), gz._stream(None)), "compress")
+    torch.cuda.synchronize()
+    return out[:int(nb.item())].cpu().numpy()
+
+
+def random_blob(seed):
+    from paper_2308_05199_amd import selector
+    g = np.random.default_rng(seed)
+    w = g.normal(0, 0.3, mlp.NPARAM).astype(np.float32)
+    feats = g.integers(0, 32, (500, 16)).astype(np.int8)
+    return selector.export_int8(w, feats)
+
+
+@pytest.mark.parametrize("select", [1, 2, 0])
+@pytest.mark.parametrize("threads", [128, 256])
+def test_tile_compress_matches_oracle(gz, ctx, oracle, select, threads):
+    from paper_2308_05199_amd import selector
+    say("tiles", select, threads)
+    blob = random_blob(7)
+    selector.load(ctx, blob)
+    for x, nx, eb in fields():
+        want = oracle.compress(x, eb, block_len=64, mode=1, nx=nx, select=select, blob=blob)
+        got = gpu_tile_stream(gz, ctx, x, nx, eb, select, threads)
+        assert got.tobytes() == want.tobytes(), (nx, select)
+    assert ctx.device_status() == 0
+
+
+def test_tile_decompress_matches_oracle(gz, ctx, oracle):
+    import ctypes
+    import torch
+    say("tile decompress")
+    for x, nx, eb in fields():
+        x = x.copy()
+        x[100] = np.nan
+        for select in (1, 2):
+            s = oracle.compress(x, eb, block_len=64, mode=1, nx=nx, select=select)
+            want = oracle.decompress(s)
+            y = torch.empty(x.size, dtype=torch.float32, device="cuda")
+            p = tile_params(gz, nx, 0)
+            sd = dev(s)
+            gz.check(gz.gz_decompress(ctx.h, gz._ptr(sd), s.size, x.size, gz.GZ_F32,
+                                      ctypes.byref(p), gz._ptr(y), gz._stream(None)), "decomp")
+            torch.cuda.synchronize()
+            assert y.cpu().numpy().tobytes() == want.tobytes(), (nx, select)
+    assert ctx.device_status() == 0
+
+
+def test_tile_trial_matches_oracle(gz, ctx, oracle):
+    from paper_2308_05199_amd import selector
+    say("tile trial")
+    for x, nx, eb in fields():
+        f, s, lab = selector.trial(ctx, dev(x), nx, eb)
+        import torch
+        torch.cuda.synchronize()
+        wf, ws, wl = oracle.tile_trial(x, nx, eb)
+        f, s, lab = f.cpu().numpy(), s.cpu().numpy().astype(np.uint32), lab.cpu().numpy()
+        assert np.array_equal(lab, wl)
+        keep = wl != 255
+        assert np.array_equal(f[keep], wf[keep])
+        assert np.array_equal(s[keep], ws[keep])
+
+
+def test_training_gradient_matches_oracle(gz, ctx):
+    import torch
+    from paper_2308_05199_amd import selector
+    say("mlp grad")
+    g = np.random.default_rng(3)
+    w = g.normal(0, 0.2, mlp.NPARAM).astype(np.float32)
+    feat = g.integers(0, 32, (20000, 16)).astype(np.int8)
+    label = g.integers(0, 3, 20000).astype(np.uint8)
+    label[::13] = 255
+    gg, loss = selector.grad(ctx, dev(w), dev(feat), dev(label))
+    torch.cuda.synchronize()
+    wl, wg = mlp.loss_and_grad(w.astype(np.float64), feat, label)
+    gg = gg.cpu().numpy().astype(np.float64)
+    scale = np.abs(wg).max()
+    assert np.all(np.abs(gg - wg) <= 1e-4 * np.maximum(np.abs(wg), 1e-2 * scale))
+    assert abs(float(loss.item()) - wl) <= 1e-4 * abs(wl)
+
+
+def test_adam_step_matches_formula(gz, ctx):
+    import ctypes
+    import torch
+    say("adam")
+    g = np.random.default_rng(4)
+    w = g.normal(0, 1, mlp.NPARAM).astype(np.float32)
+    gr = g.normal(0, 1, mlp.NPARAM).astype(np.float32)
+    W, G = dev(w), dev(gr)
+    M, V = torch.zeros_like(W), torch.zeros_like(W)
+    gz.check(gz.gz_mlp_adam(ctx.h, gz._ptr(W), gz._ptr(G), gz._ptr(M), gz._ptr(V), 1,
+                            ctypes.c_float(1e-2), gz._stream(None)), "adam")
+    torch.cuda.synchronize()
+    m = 0.1 * gr.astype(np.float64)
+    v = 0.001 * gr.astype(np.float64) ** 2
+    want = w - 1e-2 * (m / 0.1) / (np.sqrt(v / 0.001) + 1e-8)
+    assert np.allclose(W.cpu().numpy(), want, rtol=1e-5, atol=1e-6)
