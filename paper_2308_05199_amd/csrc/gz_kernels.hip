@@ -354,6 +354,117 @@ __device__ __forceinline__ uint32_t plane_of(const uint32_t (&a)[32], uint32_t j
   return p;
 }
 
+// ---- coalesced strip transfers through LDS.  A strip's raw values sit in
+// LDS segment by segment with 4 dwords of padding after each 32-element
+// segment, so 16-byte global accesses stay contiguous across lanes and the
+// per-lane 16-byte LDS accesses hit distinct banks.
+template <typename T>
+__device__ __forceinline__ constexpr uint32_t seg_stride() {
+  return 32 * (sizeof(T) / 4) + 4;
+}
+
+// Loads strip values src[0 .. TPB*32) (nvalid of them valid, the rest 0)
+// into the LDS segment layout.
+template <typename T>
+__device__ __forceinline__ void strip_to_lds(const T* __restrict__ src, uint64_t nvalid) {
+  constexpr uint32_t SEGW = 32 * (sizeof(T) / 4), STR = seg_stride<T>();
+  const uint32_t tid = threadIdx.x, TPB = blockDim.x;
+  const uint32_t nch = TPB * SEGW / 4;  // 16-byte chunks
+  const uint32_t* s32 = (const uint32_t*)src;
+  const uint64_t vdw = nvalid * (sizeof(T) / 4);
+  uint32_t* buf = g_stage + 4;
+  for (uint32_t k0 = 0; k0 < nch; k0 += 4 * TPB) {
+    u4u r[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t k = k0 + u * TPB + tid;
+      const uint64_t dw = 4ull * k;
+      if (k < nch && dw + 4 <= vdw) {
+        r[u] = *(const u4u*)(s32 + dw);
+      } else {
+        r[u].x = (k < nch && dw + 0 < vdw) ? s32[dw + 0] : 0u;
+        r[u].y = (k < nch && dw + 1 < vdw) ? s32[dw + 1] : 0u;
+        r[u].z = (k < nch && dw + 2 < vdw) ? s32[dw + 2] : 0u;
+        r[u].w = 0u;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint32_t k = k0 + u * TPB + tid;
+      if (k < nch) {
+        const uint32_t dw = 4 * k;
+        *(u4u*)(buf + (dw / SEGW) * STR + dw % SEGW) = r[u];
+      }
+    }
+  }
+}
+
+// Stores the LDS segment layout to dst[0 .. nvalid) with 16-byte stores.
+template <typename T>
+__device__ __forceinline__ void lds_to_strip(T* __restrict__ dst, uint64_t nvalid) {
+  constexpr uint32_t SEGW = 32 * (sizeof(T) / 4), STR = seg_stride<T>();
+  const uint32_t tid = threadIdx.x, TPB = blockDim.x;
+  const uint64_t vdw = nvalid * (sizeof(T) / 4);
+  const uint32_t nch = (uint32_t)min((uint64_t)TPB * SEGW / 4, (vdw + 3) / 4);
+  uint32_t* d32 = (uint32_t*)dst;
+  const uint32_t* buf = g_stage + 4;
+  for (uint32_t k = tid; k < nch; k += TPB) {
+    const uint32_t dw = 4 * k;
+    const u4u r = *(const u4u*)(buf + (dw / SEGW) * STR + dw % SEGW);
+    if (dw + 4 <= vdw) {
+      *(u4u*)(d32 + dw) = r;
+    } else {
+      if (dw + 0 < vdw) d32[dw + 0] = r.x;
+      if (dw + 1 < vdw) d32[dw + 1] = r.y;
+      if (dw + 2 < vdw) d32[dw + 2] = r.z;
+    }
+  }
+}
+
+// The lane's own segment in the LDS layout.
+template <typename T>
+__device__ __forceinline__ void lane_from_lds(T (&v)[32]);
+template <>
+__device__ __forceinline__ void lane_from_lds<float>(float (&v)[32]) {
+  const f4u* p = (const f4u*)(g_stage + 4 + threadIdx.x * seg_stride<float>());
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const f4u r = p[k];
+    v[4 * k] = r.x; v[4 * k + 1] = r.y; v[4 * k + 2] = r.z; v[4 * k + 3] = r.w;
+  }
+}
+template <>
+__device__ __forceinline__ void lane_from_lds<double>(double (&v)[32]) {
+  const d2u* p = (const d2u*)(g_stage + 4 + threadIdx.x * seg_stride<double>());
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const d2u r = p[k];
+    v[2 * k] = r.x; v[2 * k + 1] = r.y;
+  }
+}
+template <typename T>
+__device__ __forceinline__ void lane_to_lds(const T (&v)[32]);
+template <>
+__device__ __forceinline__ void lane_to_lds<float>(const float (&v)[32]) {
+  f4u* p = (f4u*)(g_stage + 4 + threadIdx.x * seg_stride<float>());
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    f4u r;
+    r.x = v[4 * k]; r.y = v[4 * k + 1]; r.z = v[4 * k + 2]; r.w = v[4 * k + 3];
+    p[k] = r;
+  }
+}
+template <>
+__device__ __forceinline__ void lane_to_lds<double>(const double (&v)[32]) {
+  d2u* p = (d2u*)(g_stage + 4 + threadIdx.x * seg_stride<double>());
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    d2u r;
+    r.x = v[2 * k]; r.y = v[2 * k + 1];
+    p[k] = r;
+  }
+}
+
 // Where the lane's block sits in the incoming payload (dwords from the
 // payload start) and how it is coded; lets the fused step re-read a block.
 struct DecInfo {
@@ -1107,8 +1218,11 @@ __device__ __forceinline__ void compress_body(const Job& J, uint64_t s, uint64_t
   const uint64_t seg = s * blockDim.x + threadIdx.x;
   const uint64_t e0 = seg * SEG;
   const uint32_t vcnt = FULL ? 32u : (e0 >= J.n ? 0u : (uint32_t)min((uint64_t)SEG, J.n - e0));
+  const uint64_t s0 = s * blockDim.x * (uint64_t)SEG;
+  strip_to_lds<T>((const T*)J.in + s0, FULL ? (uint64_t)blockDim.x * SEG : J.n - s0);
+  __syncthreads();
   T v[32];
-  load_seg<T>((const T*)J.in + (vcnt ? e0 : 0), vcnt, v);
+  lane_from_lds<T>(v);
   encode_strip<T, L, FULL, false>(J, s, gs, C, sm, v, vcnt, nullptr, false);
 }
 
@@ -1130,7 +1244,11 @@ __device__ __forceinline__ void decompress_body(const Job& J, uint64_t s, const 
   T v[32];
   DecInfo di;
   if (decode_strip<T, L, FULL>(J, in, avail, s, C, sm, v, vcnt, di)) {
-    if (vcnt) store_seg<T>((T*)J.out + e0, vcnt, v);
+    __syncthreads();  // every lane has read its payload words
+    lane_to_lds<T>(v);
+    __syncthreads();
+    const uint64_t s0 = s * blockDim.x * (uint64_t)SEG;
+    lds_to_strip<T>((T*)J.out + s0, FULL ? (uint64_t)blockDim.x * SEG : J.n - s0);
   }
 }
 
@@ -1153,8 +1271,12 @@ __device__ __forceinline__ void fused_body(const Job& J, uint64_t s, uint64_t gs
   fs.pay = (const uint32_t*)((const uint8_t*)J.in + J.pay_off);
   fs.t = sm.t32;
   fs.exists = FULL || (s * blockDim.x + threadIdx.x) / (L / 32) < J.B;
+  __syncthreads();  // every lane has read its payload words
+  const uint64_t s0 = s * blockDim.x * (uint64_t)SEG;
+  strip_to_lds<float>(J.local + s0, FULL ? (uint64_t)blockDim.x * SEG : J.n - s0);
+  __syncthreads();
   float a[32];
-  load_seg<float>(J.local + (vcnt ? e0 : 0), vcnt, a);
+  lane_from_lds<float>(a);
 #pragma unroll
   for (int i = 0; i < 32; ++i) v[i] = v[i] + a[i];  // incoming + local, fp32
   encode_strip<float, L, FULL, true>(J, s, gs, C, sm, v, vcnt, &fs, !ok);
@@ -1188,7 +1310,8 @@ __device__ __forceinline__ void fused_one(const Job& J, uint64_t s, uint64_t gs,
 #define GZ_FUSED_ATTR __launch_bounds__(MAX_TPB) __attribute__((amdgpu_waves_per_eu(3, 8)))
 
 template <typename T, int L>
-__global__ GZ_KERNEL_ATTR void k_compress(Job J, Ctl C) {
+__global__ __launch_bounds__(MAX_TPB)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 3 : 4, 8))) void k_compress(Job J, Ctl C) {
   GZ_STRIP_LOOP(J.nstrips, (compress_one<T, L>(J, t, t, C, sm)))
 }
 
@@ -1245,7 +1368,7 @@ __device__ __forceinline__ void batch_body(const Job* __restrict__ jobs,
 
 template <uint32_t OP, bool WIDE>
 __global__ __launch_bounds__(MAX_TPB)
-__attribute__((amdgpu_waves_per_eu(OP == 2 ? 3 : 4, 8))) void k_batch(const Job* __restrict__ jobs,
+__attribute__((amdgpu_waves_per_eu(OP == 2 || (OP == 0 && WIDE) ? 3 : 4, 8))) void k_batch(const Job* __restrict__ jobs,
                                        const uint32_t* __restrict__ strip_job, uint32_t total,
                                        Ctl C) {
   GZ_STRIP_LOOP(total, (batch_body<OP, WIDE>(jobs, strip_job, t, C, sm)))
@@ -1418,7 +1541,7 @@ __global__ void k_reset(Ctl C) {
 // ------------------------------------------------------------ launchers
 // Dynamic LDS: the strip staging buffer (largest strip payload + headroom).
 static size_t stage_bytes(uint32_t dtype, uint32_t tpb) {
-  return 32 + (size_t)tpb * SEG * (dtype == 0 ? 4 : 8);
+  return 32 + (size_t)tpb * (SEG * (dtype == 0 ? 1 : 2) + 4) * 4;  // padded segment layout
 }
 
 template <typename T, int L>
