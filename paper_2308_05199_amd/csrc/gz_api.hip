@@ -56,8 +56,9 @@ struct gz_ctx {
   int stage_next = 0;
   size_t stage_bytes = 0;
   Tuned tuned[3][2][3];  // [op][dtype][log2L-5]
+  uint64_t wait_ticks = 0;    // one second of the device's constant-rate clock
   float* train_ws = nullptr;  // selector training: per-sample backward terms
-  Ctl ctl() const { return Ctl{ctrl, status, jobbase, blob}; }
+  Ctl ctl() const { return Ctl{ctrl, status, jobbase, blob, wait_ticks}; }
 };
 
 struct gz_plan {
@@ -277,6 +278,11 @@ gz_status gz_ctx_create(gz_ctx** out, int device, uint64_t max_elems, uint32_t m
     delete c;
     return GZ_EHIP;
   }
+  int wclk_khz = 0;
+  if (hipDeviceGetAttribute(&wclk_khz, hipDeviceAttributeWallClockRate, device) != hipSuccess ||
+      wclk_khz <= 0)
+    wclk_khz = 100000;
+  c->wait_ticks = (uint64_t)wclk_khz * 1000ull;
   c->max_elems = max_elems;
   c->max_jobs = max_requests;
   // strips of the smallest workgroup (128 lanes = 4096 elements), plus one
@@ -675,8 +681,9 @@ static bool cache_lookup(const char* path, const std::string& key, uint32_t& tpb
   while (fgets(line, sizeof line, f)) {
     char k[256];
     unsigned t, g;
+    // entries with a workgroup size or grid the kernels do not take are ignored
     if (sscanf(line, " {\"key\": \"%255[^\"]\", \"tpb\": %u, \"grid\": %u", k, &t, &g) == 3 &&
-        key == k) {
+        key == k && (t == 128 || t == 256) && g >= 1 && g <= 65536) {
       tpb = t;
       grid = g;
       hit = true;
@@ -819,6 +826,7 @@ gz_status gz_tile_trial(gz_ctx* c, const float* d_in, uint64_t n, uint32_t nx, d
   J.dtype = GZ_F32;
   if (!set_bound(J, GZ_F32, eb)) return GZ_EINVAL;
   if (!n) return GZ_OK;
+  J.in = d_in;
   J.n = n;
   J.B = n / 64;
   J.nx = nx;

@@ -51,6 +51,7 @@ struct Ctl {
   unsigned long long* status;   // one look-back word per global strip
   unsigned long long* jobbase;  // one word per job of a packed chain
   const uint8_t* blob;          // selector weights
+  uint64_t wait_ticks;          // longest inter-workgroup wait (constant-rate clock ticks)
 };
 
 }  // namespace gzk

@@ -262,6 +262,18 @@ __device__ __forceinline__ bool aborted(const Ctl& C) {
   return (ld_agent32(&C.ctrl->err) & ERRF_TIMEOUT) != 0;
 }
 
+// Bound of every inter-workgroup wait: C.wait_ticks of the constant-rate
+// clock from the first unsuccessful poll (or SPIN_LIMIT polls), or another
+// workgroup's timeout.  Checked every 64 polls.
+__device__ __forceinline__ bool wait_over(const Ctl& C, uint32_t spins, uint64_t& t0) {
+  if (spins == 1) {
+    t0 = (uint64_t)wall_clock64();
+    return false;
+  }
+  if ((spins & 63u) != 0) return false;
+  return spins > SPIN_LIMIT || (uint64_t)wall_clock64() - t0 > C.wait_ticks || aborted(C);
+}
+
 // Publishes the strip aggregate (or, at the head of a chain, its prefix).
 __device__ __forceinline__ void publish_agg(const Ctl& C, uint64_t gs, uint64_t chain0,
                                             uint32_t ep, uint64_t agg) {
@@ -278,6 +290,7 @@ __device__ uint64_t lookback(const Ctl& C, uint64_t gs, uint64_t chain0, uint32_
   uint64_t excl = 0;
   int64_t top = (int64_t)gs - 1;
   uint32_t spins = 0;
+  uint64_t t0 = 0;
   for (;;) {
     int64_t idx = top - lane;
     uint32_t flag;
@@ -297,7 +310,7 @@ __device__ uint64_t lookback(const Ctl& C, uint64_t gs, uint64_t chain0, uint32_
     uint64_t upto = p >= 63 ? ~0ull : ((2ull << p) - 1);
     if (zm & upto) {
       ++spins;
-      if (spins > SPIN_LIMIT || ((spins & 255u) == 0 && aborted(C))) {
+      if (wait_over(C, spins, t0)) {
         timeout = true;
         break;
       }
@@ -315,12 +328,13 @@ __device__ uint64_t lookback(const Ctl& C, uint64_t gs, uint64_t chain0, uint32_
 // Chain prefix at the first strip of job j (packed Scatter output).
 __device__ uint64_t job_base_wait(const Ctl& C, uint32_t j, uint32_t ep, bool& timeout) {
   uint32_t spins = 0;
+  uint64_t t0 = 0;
   for (;;) {
     uint64_t w = ld_agent(C.jobbase + j);
     if ((uint32_t)((w >> 34) & 0x0FFFFFFFu) == (ep & 0x0FFFFFFFu) && (w >> 62) == 2)
       return w & VMASK;
     ++spins;
-    if (spins > SPIN_LIMIT || ((spins & 255u) == 0 && aborted(C))) {
+    if (wait_over(C, spins, t0)) {
       timeout = true;
       return 0;
     }
@@ -1012,10 +1026,12 @@ __device__ void check_header(const Job& J, const uint8_t* in, uint64_t in_bytes,
       sm.t32 = t32;
       sm.t64 = t64;
       sm.paydw = payload / 4;
-      sm.hdr_job = J.job + 1;
     }
   }
   __syncthreads();
+  // Marked checked only after the barrier: every wave has then read the old
+  // mark and entered this function, so all of them take the same barriers.
+  if (tid == 0) sm.hdr_job = J.job + 1;
 }
 
 template <typename T>
@@ -1654,6 +1670,10 @@ hipError_t launch_tiles(uint32_t op, const Job& J, const Ctl& C, uint32_t tpb, u
 
 hipError_t launch_tile_trial(const Job& J, int8_t* feat, uint32_t* sizes, uint8_t* label,
                              hipStream_t st) {
+  // every tile is read from J.in and written to the three outputs
+  if (J.B && (!J.in || !feat || !sizes || !label || J.nx == 0 || J.nx % 8 != 0 ||
+              J.n != 64 * J.B || J.n % (8ull * J.nx) != 0))
+    return hipErrorInvalidValue;
   const uint64_t segs = 2 * J.B;
   uint64_t blocks = (segs + 255) / 256;
   const uint32_t grid = (uint32_t)(blocks < 8192 ? (blocks ? blocks : 1) : 8192);
