@@ -12,6 +12,7 @@ sum-of-sinusoids field, the roofline of the dominant kernel (the batched
 fused step) and the CPU oracle timed on the full reduce-scatter.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -39,6 +40,8 @@ def parse():
     ap.add_argument("--no-headline", action="store_true", help="skip the 1 GiB compress/decompress")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (scales profiler byte counters)")
+    ap.add_argument("--extras", default="",
+                    help="comma list of extra measurements: scatter,batch,selector")
     return ap.parse_args()
 
 
@@ -53,6 +56,11 @@ def traffic_from_profiles():
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             vals[k.strip()] = v.strip()
+    src = os.path.join(ROOT, "paper_2308_05199_amd", "csrc", "gz_kernels.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if vals.get("kernel_source_sha256") != sha:
+        return None  # counters taken on another version of the kernels
     try:
         return float(vals["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
@@ -107,6 +115,174 @@ def headline(ctx, gz, torch, reps=10):
     return res
 
 
+def _timed(torch, fn, reps=5):
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def device_frames(torch, nframes, h=2048, w=2048, seed=0):
+    """Frame recipe of synth.frames (gradient background + Poisson(50) +
+    1e-4 point sources with a sigma-1 Gaussian PSF), drawn on the device."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    yy = torch.arange(h, device="cuda", dtype=torch.float32).view(h, 1)
+    xx = torch.arange(w, device="cuda", dtype=torch.float32).view(1, w)
+    out = torch.empty((nframes, h, w), device="cuda")
+    r = torch.arange(-3, 4, device="cuda", dtype=torch.float32)
+    psf = torch.exp(-(r.view(-1, 1) ** 2 + r.view(1, -1) ** 2) / 2)
+    for f in range(nframes):
+        a = 100 + 100 * torch.rand(1, device="cuda", generator=g)
+        b, c = (torch.rand(2, device="cuda", generator=g) - 0.5) * 0.1
+        img = a + b * xx + c * yy
+        img = img + torch.poisson(torch.full((h, w), 50.0, device="cuda"), generator=g)
+        ns = int(1e-4 * h * w)
+        ys = torch.randint(3, h - 3, (ns,), device="cuda", generator=g)
+        xs = torch.randint(3, w - 3, (ns,), device="cuda", generator=g)
+        pk = 1e3 + 9e3 * torch.rand(ns, device="cuda", generator=g)
+        src = torch.zeros((h, w), device="cuda")
+        src.index_put_((ys, xs), pk, accumulate=True)
+        img = img + torch.nn.functional.conv2d(src.view(1, 1, h, w), psf.view(1, 1, 7, 7),
+                                               padding=3).view(h, w)
+        out[f] = img
+    return out.view(-1)
+
+
+def extra_scatter(ctx, gz, torch):
+    """64 frames of 2048^2 (1 GiB) in 64 log-uniform chunks of 1-64 MiB,
+    eb 1e-3: one persistent compress launch, one batched decompress."""
+    import numpy as np
+    from paper_2308_05199_amd import synth
+    root = device_frames(torch, 64)
+    counts, displs = synth.loguniform_counts(root.numel(), 64, 1 << 18, 1 << 24, seed=1)
+    eb = 1e-3
+    out, cb, co = ctx.scatter_compress(root, counts, displs, eb)
+    torch.cuda.synchronize()
+    total = int((co[-1] + cb[-1]).item())
+    y = torch.empty_like(root)
+    tc = _timed(torch, lambda: ctx.scatter_compress(root, counts, displs, eb, out=out))
+    td = _timed(torch, lambda: ctx.scatter_decompress(out, co, counts, displs, out=y,
+                                                     packed_bytes=total))
+    err = float((y.double() - root.double()).abs().max())
+    raw = 4 * root.numel()
+    return {"workload": "64 x 2048^2 fp32 frames, 64 chunks log-uniform 1-64 MiB, eb 1e-3",
+            "ratio": raw / total, "max_abs_err": err,
+            "compress_ms": tc, "compress_GBps": raw / tc / 1e6,
+            "compress_hbm_frac": (raw + total) / tc / 1e6 / HBM_PEAK_GBPS,
+            "decompress_ms": td, "decompress_GBps": raw / td / 1e6,
+            "decompress_hbm_frac": (raw + total) / td / 1e6 / HBM_PEAK_GBPS}
+
+
+def extra_batch(ctx, gz, torch, nreq=4096):
+    """4096 independent requests, log-uniform 4 KiB-16 MiB, fp32/fp64, eb
+    log-uniform in [1e-6,1e-2]: one persistent launch (replayed as a graph)
+    against one launch per request."""
+    import numpy as np
+    from paper_2308_05199_amd import synth
+    reqs = synth.mixed_requests(nreq, seed=0, lo_bytes=4096, hi_bytes=16 << 20)
+    ctx = gz.Context(0, max_elems=sum(r["n"] for r in reqs) + 1, max_requests=nreq)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    items, ins, outs, nbs = [], [], [], []
+    raw = 0
+    for i, r in enumerate(reqs):
+        dt = torch.float32 if r["dtype"] == np.float32 else torch.float64
+        n = r["n"]
+        if r["kind"] == "grf":   # smooth random walk, unit variance
+            x = torch.cumsum(torch.randn(n, device="cuda", generator=g, dtype=torch.float64), 0)
+            x = (x - x.mean()) / x.std().clamp_min(1e-30)
+        else:                    # image-like row: gradient + Poisson(50)
+            base = 100 + 100 * torch.rand(1, device="cuda", generator=g, dtype=torch.float64)
+            x = (base + torch.poisson(torch.full((n,), 50.0, device="cuda", dtype=torch.float64),
+                                      generator=g)) / 100
+        x = x.to(dt)
+        code = gz.GZ_F32 if dt == torch.float32 else gz.GZ_F64
+        cap = gz.bound(n, code, 32)
+        o = torch.empty(cap, dtype=torch.uint8, device="cuda")
+        nb = torch.zeros(1, dtype=torch.int64, device="cuda")
+        ins.append(x)
+        outs.append(o)
+        nbs.append(nb)
+        items.append({"in": x, "out": o, "out_bytes": nb, "n": n, "out_cap": cap,
+                      "eb": r["eb"], "dtype": code, "block_len": 32})
+        raw += x.numel() * x.element_size()
+    arr = ctx.requests(items)
+    plan = ctx.plan(gz.GZ_OP_COMPRESS, arr)
+    graph = gz.Graph([plan])
+    tg = _timed(torch, lambda: graph.launch(), reps=3)
+    comp = sum(int(nb.item()) for nb in nbs)
+
+    def one_by_one():
+        for x, o, nb, r in zip(ins, outs, nbs, reqs):
+            ctx.compress(x, r["eb"], out=o, out_bytes=nb)
+    t1 = _timed(torch, one_by_one, reps=1)
+    return {"workload": f"{len(reqs)} requests, log-uniform 4 KiB-16 MiB, fp32/fp64, "
+                        "eb log-uniform 1e-6..1e-2, L 32",
+            "raw_bytes": raw, "ratio": raw / comp,
+            "batched_graph_ms": tg, "batched_GBps": raw / tg / 1e6,
+            "batched_hbm_frac": (raw + comp) / tg / 1e6 / HBM_PEAK_GBPS,
+            "one_launch_per_request_ms": t1, "one_launch_per_request_GBps": raw / t1 / 1e6}
+
+
+def extra_selector(ctx, gz, torch):
+    """Learned predictor selection on mixed fields (GRF, images, 50%-zero
+    sparse; 8x8 tiles): train on seed-disjoint fields, then compare the
+    int8 network with exhaustive trial, fixed L1D tiles and 1D blocks on
+    ratio and compress throughput."""
+    import ctypes
+    from paper_2308_05199_amd import selector, synth
+    train_f = synth.selector_fields(1000, grf_shape=(64, 256, 256), n_images=4,
+                                    image_hw=(1024, 1024), sparse_n=1 << 22)
+    feats, labels = [], []
+    for x, nx, eb in train_f:
+        f, s, l = selector.trial(ctx, torch.from_numpy(x).cuda(), nx, eb)
+        feats.append(f)
+        labels.append(l)
+    feat = torch.cat(feats)
+    lab = torch.cat(labels)
+    w = selector.train(ctx, feat, lab, steps=1500, log=log)
+    keep = (lab < 3).nonzero().view(-1)
+    calib = feat[keep[:: max(1, keep.numel() // 50000)]].cpu().numpy()
+    blob = selector.export_int8(w.cpu().numpy(), calib)
+    selector.load(ctx, blob)
+    test_f = synth.selector_fields(0, grf_shape=(128, 256, 256), n_images=8,
+                                   image_hw=(1024, 1024), sparse_n=1 << 23)
+    res = {"mlp": [0, 0.0], "exhaustive": [0, 0.0], "l1d_tiles": [0, 0.0], "blocks_1d": [0, 0.0]}
+    raw = 0
+    for x, nx, eb in test_f:
+        xd = torch.from_numpy(x).cuda()
+        raw += 4 * x.size
+        cap = gz.bound(x.size, gz.GZ_F32, 64)
+        out = torch.empty(gz.bound(x.size, gz.GZ_F32, 32), dtype=torch.uint8, device="cuda")
+        nb = torch.zeros(1, dtype=torch.int64, device="cuda")
+        for key, sel in (("mlp", 0), ("exhaustive", 1), ("l1d_tiles", 2)):
+            p = gz.gz_params(64, 0, 0, 1, sel, nx)
+            run = lambda: gz.check(gz.gz_compress(ctx.h, gz._ptr(xd), x.size, gz.GZ_F32, eb,
+                                                  ctypes.byref(p), gz._ptr(out), cap,
+                                                  gz._ptr(nb), gz._stream(None)), "tiles")
+            t = _timed(torch, run)
+            res[key][0] += int(nb.item())
+            res[key][1] += t
+        t = _timed(torch, lambda: ctx.compress(xd, eb, out=out, out_bytes=nb))
+        res["blocks_1d"][0] += int(nb.item())
+        res["blocks_1d"][1] += t
+    out = {"workload": "mixed fields (3D GRF rows, noisy images, 50%-zero sparse), 8x8 tiles, "
+                       "eb 1e-4 x range, int8 MLP 16-32-3 trained on seed-disjoint fields",
+           "elements": raw // 4}
+    for k, (b, t) in res.items():
+        out[k] = {"ratio": raw / b, "compress_GBps": raw / t / 1e6}
+    out["mlp_ratio_vs_exhaustive"] = out["mlp"]["ratio"] / out["exhaustive"]["ratio"]
+    out["mlp_speed_vs_exhaustive"] = (out["mlp"]["compress_GBps"] /
+                                      out["exhaustive"]["compress_GBps"])
+    return out
+
+
 def cpu_baseline(bufs_np, eb):
     """The oracle, unchanged, on the same reduce-scatter (all 8 chunks,
     8 operations each) on one host core."""
@@ -142,10 +318,10 @@ def main():
         a = torch.ones(1 << 28, device="cuda")
         b = torch.empty_like(a)
         for _ in range(3):
-            b.copy_(a)
+            torch.mul(a, 1.0, out=b)  # an elementwise kernel: 1 GiB read, 1 GiB written
         torch.cuda.synchronize()
         del a, b
-        log("calibration copy: 3 x 1 GiB device-to-device")
+        log("calibration copy: 3 x 1 GiB elementwise x * 1.0")
     log("generating 8 x 256^3 ranks")
     bufs_np = synth.ring_ranks(N_RANKS, SHAPE, seed=0)
     eb = synth.relative_eb(bufs_np, 1e-4)
@@ -218,6 +394,11 @@ def main():
     streams, sizes = ring.result()
     ratio = float(raw_chunk.sum() / sizes.cpu().numpy().sum())
     head = None if args.no_headline else headline(ctx, gzccl, torch)
+    extras = {}
+    for name in [e for e in args.extras.split(",") if e]:
+        log("extra:", name)
+        extras[name] = {"scatter": extra_scatter, "batch": extra_batch,
+                        "selector": extra_selector}[name](ctx, gzccl, torch)
     cpu = None if args.no_cpu else cpu_baseline(bufs_np, eb)
 
     raw_step = N_RANKS * n * 4
@@ -260,6 +441,8 @@ def main():
                      "traffic": traffic},
         "cpu_baseline": cpu,
     }
+    if extras:
+        out["extras"] = extras
     print(json.dumps(out), flush=True)
 
 
