@@ -282,7 +282,11 @@ __device__ __forceinline__ void publish_agg(const Ctl& C, uint64_t gs, uint64_t 
 
 // Decoupled look-back run by wave 0 after publish_agg: returns the exclusive
 // prefix (dwords) of strip gs within its chain and publishes its inclusive
-// prefix.  Looks back 64 strips per probe.
+// prefix.  One probe reads LB_SUB x 64 predecessors (LB_SUB independent loads
+// per lane); sub-windows resolved before a not-yet-published word are added
+// in before the probe is retried from there.
+constexpr int LB_SUB = 4;
+
 __device__ uint64_t lookback(const Ctl& C, uint64_t gs, uint64_t chain0, uint32_t ep,
                              uint64_t agg, bool& timeout) {
   const int lane = __lane_id();
@@ -292,34 +296,51 @@ __device__ uint64_t lookback(const Ctl& C, uint64_t gs, uint64_t chain0, uint32_
   uint32_t spins = 0;
   uint64_t t0 = 0;
   for (;;) {
-    int64_t idx = top - lane;
-    uint32_t flag;
-    uint64_t val;
-    if (idx >= (int64_t)chain0) {
-      uint64_t w = ld_agent(C.status + idx);
-      bool cur = (uint32_t)((w >> 34) & 0x0FFFFFFFu) == (ep & 0x0FFFFFFFu);
-      flag = cur ? (uint32_t)(w >> 62) : 0u;
-      val = w & VMASK;
-    } else {
-      flag = 2;
-      val = 0;
+    uint32_t flag[LB_SUB];
+    uint64_t val[LB_SUB];
+#pragma unroll
+    for (int m = 0; m < LB_SUB; ++m) {
+      const int64_t idx = top - 64 * m - lane;
+      if (idx >= (int64_t)chain0) {
+        const uint64_t w = ld_agent(C.status + idx);
+        const bool cur = (uint32_t)((w >> 34) & 0x0FFFFFFFu) == (ep & 0x0FFFFFFFu);
+        flag[m] = cur ? (uint32_t)(w >> 62) : 0u;
+        val[m] = w & VMASK;
+      } else {
+        flag[m] = 2;
+        val[m] = 0;
+      }
     }
-    uint64_t pm = __ballot(flag == 2);
-    uint64_t zm = __ballot(flag == 0);
-    int p = pm ? (int)__builtin_ctzll(pm) : 64;
-    uint64_t upto = p >= 63 ? ~0ull : ((2ull << p) - 1);
-    if (zm & upto) {
+    uint64_t part = 0;  // this lane's share of the resolved sub-windows
+    int resolved = 0;   // sub-windows fully added in
+    bool done = false, wait = false;
+#pragma unroll
+    for (int m = 0; m < LB_SUB; ++m) {
+      if (!done && !wait) {
+        const uint64_t pm = __ballot(flag[m] == 2);
+        const uint64_t zm = __ballot(flag[m] == 0);
+        const int p = pm ? (int)__builtin_ctzll(pm) : 64;
+        const uint64_t upto = p >= 63 ? ~0ull : ((2ull << p) - 1);
+        if (zm & upto) {
+          wait = true;
+        } else {
+          part += lane <= p ? val[m] : 0ull;
+          ++resolved;
+          done = p < 64;
+        }
+      }
+    }
+    excl += wave_sum64(part);
+    if (done) break;
+    top -= 64 * resolved;
+    if (wait) {
       ++spins;
       if (wait_over(C, spins, t0)) {
         timeout = true;
         break;
       }
       __builtin_amdgcn_s_sleep(1);
-      continue;
     }
-    excl += wave_sum64(lane <= p ? val : 0ull);
-    if (p < 64) break;
-    top -= 64;
   }
   if (lane == 0) st_agent(C.status + gs, sw_pack(2, ep, timeout ? 0 : excl + agg));
   return excl;
@@ -361,11 +382,93 @@ __device__ __forceinline__ uint32_t strip_scan(uint32_t contrib, Smem& sm, uint3
 }
 
 // Magnitude plane j of a segment: bit i = bit j of a[i].
-__device__ __forceinline__ uint32_t plane_of(const uint32_t (&a)[32], uint32_t j) {
-  uint32_t p = 0;
+// ---- bit planes.  Plane j of a lane's 32 magnitudes a[i] is the word whose
+// bit i is bit j of a[i].  Planes are moved 8 at a time: the bytes 8g..8g+7
+// of eight magnitudes form an 8x8 bit matrix (one byte per element) that a
+// three-stage delta swap transposes into one byte per plane.
+
+// v_perm_b32: byte k of the result is byte sel.k of the 8-byte value
+// (hi:lo); selector 0x0C yields a zero byte.
+__device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel) {
+  return __builtin_amdgcn_perm(hi, lo, sel);
+}
+// Selector taking byte b of x0..x3 (as lo, hi pairs (x0, x1), (x2, x3)).
+__device__ __forceinline__ uint32_t sel_lo(uint32_t b) { return 0x0C0C0000u | ((4u + b) << 8) | b; }
+__device__ __forceinline__ uint32_t sel_hi(uint32_t b) { return ((4u + b) << 24) | (b << 16) | 0x0C0Cu; }
+// Byte b of four words, gathered into one word (x0's byte lowest).
+__device__ __forceinline__ uint32_t gather4(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
+                                            uint32_t b) {
+  return perm(x1, x0, sel_lo(b)) | perm(x3, x2, sel_hi(b));
+}
+
+// 8x8 bit transpose of the 64-bit value hi:lo (bit c of byte r <-> bit r of
+// byte c).
+__device__ __forceinline__ void tr8x8(uint32_t& lo, uint32_t& hi) {
+  uint32_t t;
+  t = ((lo >> 7) ^ lo) & 0x00AA00AAu;
+  lo ^= t | (t << 7);
+  t = ((hi >> 7) ^ hi) & 0x00AA00AAu;
+  hi ^= t | (t << 7);
+  t = ((lo >> 14) ^ lo) & 0x0000CCCCu;
+  lo ^= t | (t << 14);
+  t = ((hi >> 14) ^ hi) & 0x0000CCCCu;
+  hi ^= t | (t << 14);
+  const uint32_t nl = (lo & 0x0F0F0F0Fu) | ((hi << 4) & 0xF0F0F0F0u);
+  const uint32_t nh = (hi & 0xF0F0F0F0u) | ((lo >> 4) & 0x0F0F0F0Fu);
+  lo = nl;
+  hi = nh;
+}
+
+// Writes planes 0..F-1 of a[] to dst[j * stride].
+__device__ __forceinline__ void put_planes(const uint32_t (&a)[32], uint32_t F, uint32_t* dst,
+                                           uint32_t stride) {
+  for (uint32_t g = 0; 8 * g < F; ++g) {
+    uint32_t lo[4], hi[4];
 #pragma unroll
-  for (int i = 0; i < 32; ++i) p |= ((a[i] >> j) & 1u) << i;
-  return p;
+    for (int k = 0; k < 4; ++k) {
+      lo[k] = gather4(a[8 * k], a[8 * k + 1], a[8 * k + 2], a[8 * k + 3], g);
+      hi[k] = gather4(a[8 * k + 4], a[8 * k + 5], a[8 * k + 6], a[8 * k + 7], g);
+      tr8x8(lo[k], hi[k]);
+    }
+    const uint32_t nj = min(F - 8 * g, 8u);
+#pragma unroll
+    for (uint32_t j = 0; j < 8; ++j) {
+      if (j < nj) {
+        const uint32_t b = j & 3;
+        const uint32_t word = j < 4 ? gather4(lo[0], lo[1], lo[2], lo[3], b)
+                                    : gather4(hi[0], hi[1], hi[2], hi[3], b);
+        dst[(8 * g + j) * stride] = word;
+      }
+    }
+  }
+}
+
+// Magnitudes a[] from planes src[j * stride], j < F (planes >= F are zero).
+__device__ __forceinline__ void get_planes(const uint32_t* src, uint32_t stride, uint32_t F,
+                                           uint32_t (&a)[32]) {
+#pragma unroll
+  for (int i = 0; i < 32; ++i) a[i] = 0;
+  for (uint32_t g = 0; 8 * g < F; ++g) {
+    const uint32_t nj = min(F - 8 * g, 8u);
+    uint32_t P[8];
+#pragma unroll
+    for (uint32_t j = 0; j < 8; ++j) P[j] = j < nj ? src[(8 * g + j) * stride] : 0u;
+    // a[8k+m] takes byte m of (lo, hi) of group k as its byte g
+    uint32_t sel[4];
+#pragma unroll
+    for (uint32_t b = 0; b < 4; ++b)
+      sel[b] = (0x03020100u & ~(0xFFu << (8 * g))) | ((4u + b) << (8 * g));
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      uint32_t lo = gather4(P[0], P[1], P[2], P[3], (uint32_t)k);
+      uint32_t hi = gather4(P[4], P[5], P[6], P[7], (uint32_t)k);
+      tr8x8(lo, hi);
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        a[8 * k + m] = perm(m < 4 ? lo : hi, a[8 * k + m], sel[m & 3]);
+      }
+    }
+  }
 }
 
 // ---- coalesced strip transfers through LDS.  A strip's raw values sit in
@@ -505,17 +608,8 @@ __device__ __forceinline__ void unpack_seg(const uint32_t* pw, uint32_t kind, ui
   // L1D
   const int32_t base = (int32_t)pw[0];
   uint32_t a[32];
-#pragma unroll
-  for (int i = 0; i < 32; ++i) a[i] = 0;
-  uint32_t sg = 0;
-  if (F) {
-    sg = pw[1 + w];
-    for (uint32_t j = 0; j < F; ++j) {
-      const uint32_t p = pw[1 + (j + 1) * LPB + w];
-#pragma unroll
-      for (int i = 0; i < 32; ++i) a[i] |= ((p >> i) & 1u) << j;
-    }
-  }
+  get_planes(pw + 1 + LPB + w, LPB, F, a);
+  const uint32_t sg = F ? pw[1 + w] : 0u;
   uint32_t acc = 0;
 #pragma unroll
   for (int i = 0; i < 32; ++i) {
@@ -870,7 +964,8 @@ __device__ __forceinline__ void fused_raw_stage(const Job& J, const FusedSrc& fs
 
 template <typename T, int L, int MODE, bool FUSED, bool FULL>
 __device__ void emit_strip(const Job& J, uint64_t s, uint64_t gs, const Ctl& C, Smem& sm,
-                           uint32_t vcnt, const LaneCode& lc, const FusedSrc* fs, bool skip) {
+                           uint32_t vcnt, const LaneCode& lc, const FusedSrc* fs, bool skip,
+                           uint32_t& tk) {
   constexpr int LPB = L / 32;
   constexpr uint32_t EW = sizeof(T) / 4;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -896,7 +991,7 @@ __device__ void emit_strip(const Job& J, uint64_t s, uint64_t gs, const Ctl& C, 
     }
     if (F) {
       st[o + w] = lc.sg;
-      for (uint32_t j = 0; j < F; ++j) st[o + (j + 1) * LPB + w] = plane_of(lc.a, j);
+      put_planes(lc.a, F, st + o + LPB + w, LPB);
     }
   }
   // a separate (not else) branch: the magnitudes are dead before it runs
@@ -934,6 +1029,10 @@ __device__ void emit_strip(const Job& J, uint64_t s, uint64_t gs, const Ctl& C, 
     }
   }
   __syncthreads();
+  // The workgroup's next strip is ticketed only now, once this strip's
+  // offset is known: a ticket held by a workgroup that has not started it
+  // would stall the look-back of every later strip.
+  if (tid == 0) tk = atomicAdd(&C.ctrl->ticket, 1u);
   if (sm.flag || skip) return;
 
   const uint64_t pj = sm.pj;
@@ -982,11 +1081,11 @@ __device__ void emit_strip(const Job& J, uint64_t s, uint64_t gs, const Ctl& C, 
 template <typename T, int L, bool FULL, bool FUSED>
 __device__ __forceinline__ void encode_strip(const Job& J, uint64_t s, uint64_t gs, const Ctl& C,
                                              Smem& sm, const T (&v)[32], uint32_t vcnt,
-                                             const FusedSrc* fs, bool skip) {
+                                             const FusedSrc* fs, bool skip, uint32_t& tk) {
   const uint64_t seg = s * blockDim.x + threadIdx.x;
   LaneCode lc;
   analyze_1d<T, L, FULL>(J, seg, threadIdx.x & (L / 32 - 1), v, vcnt, lc);
-  emit_strip<T, L, 0, FUSED, FULL>(J, s, gs, C, sm, vcnt, lc, fs, skip);
+  emit_strip<T, L, 0, FUSED, FULL>(J, s, gs, C, sm, vcnt, lc, fs, skip, tk);
 }
 
 // --------------------------------------------------------------- decode
@@ -1096,17 +1195,8 @@ __device__ __forceinline__ void unpack_tile(const uint32_t* pw, uint32_t kind, u
   const uint32_t o = kind == K_NONE ? 0u : 1u;
   const uint32_t base = o ? pw[0] : 0u;
   uint32_t q[32];
-#pragma unroll
-  for (int i = 0; i < 32; ++i) q[i] = 0;
-  uint32_t sg = 0;
-  if (F) {
-    sg = pw[o + w];
-    for (uint32_t j = 0; j < F; ++j) {
-      const uint32_t p = pw[o + (j + 1) * 2 + w];
-#pragma unroll
-      for (int i = 0; i < 32; ++i) q[i] |= ((p >> i) & 1u) << j;
-    }
-  }
+  get_planes(pw + o + 2 + w, 2, F, q);
+  const uint32_t sg = F ? pw[o + w] : 0u;
 #pragma unroll
   for (int i = 0; i < 32; ++i) {  // signed residuals
     const uint32_t neg = (uint32_t)__builtin_amdgcn_sbfe((int32_t)sg, i, 1);
@@ -1168,18 +1258,22 @@ __device__ bool decode_strip(const Job& J, const uint8_t* in, uint64_t in_bytes,
   const uint32_t w = tid & (LPB - 1);
   const uint64_t b = seg / LPB;
 
-  if (sm.hdr_job != J.job + 1) check_header(J, in, in_bytes, sm);
-  const bool ok = sm.hdr_ok != 0;
-  const uint64_t pay_dw = sm.paydw;
-
-  // strip payload range from the superblock table
+  // strip payload range from the superblock table; the table words are
+  // read together with the header (both lie in the stream's fixed part,
+  // readable when in_bytes reaches the payload)
   const uint32_t* table = (const uint32_t*)(in + HDR);
   const uint64_t sb0 = s * (uint64_t)(TPB * SEG / SUPER);
   const uint64_t sbn = sb0 + TPB * SEG / SUPER;
+  const bool tab_ok = in_bytes >= J.pay_off;
+  const uint32_t T0 = (tab_ok && sb0 < J.NS) ? table[sb0] : 0u;
+  const uint32_t T1 = (tab_ok && sbn < J.NS) ? table[sbn] : 0u;
+  if (sm.hdr_job != J.job + 1) check_header(J, in, in_bytes, sm);
+  const bool ok = sm.hdr_ok != 0;  // implies tab_ok
+  const uint64_t pay_dw = sm.paydw;
   uint64_t E = 0, En = 0;
   if (ok) {
-    E = sb0 < J.NS ? table[sb0] : pay_dw;
-    En = sbn < J.NS ? table[sbn] : pay_dw;
+    E = sb0 < J.NS ? T0 : pay_dw;
+    En = sbn < J.NS ? T1 : pay_dw;
   }
   const bool rng = ok && E <= En && En <= pay_dw && En - E <= (uint64_t)TPB * SEG * EW;
   const uint32_t P = rng ? (uint32_t)(En - E) : 0u;
@@ -1230,7 +1324,7 @@ __device__ bool decode_strip(const Job& J, const uint8_t* in, uint64_t in_bytes,
 // ---------------------------------------------------------------- kernels
 template <typename T, int L, bool FULL>
 __device__ __forceinline__ void compress_body(const Job& J, uint64_t s, uint64_t gs,
-                                              const Ctl& C, Smem& sm) {
+                                              const Ctl& C, Smem& sm, uint32_t& tk) {
   const uint64_t seg = s * blockDim.x + threadIdx.x;
   const uint64_t e0 = seg * SEG;
   const uint32_t vcnt = FULL ? 32u : (e0 >= J.n ? 0u : (uint32_t)min((uint64_t)SEG, J.n - e0));
@@ -1239,14 +1333,14 @@ __device__ __forceinline__ void compress_body(const Job& J, uint64_t s, uint64_t
   __syncthreads();
   T v[32];
   lane_from_lds<T>(v);
-  encode_strip<T, L, FULL, false>(J, s, gs, C, sm, v, vcnt, nullptr, false);
+  encode_strip<T, L, FULL, false>(J, s, gs, C, sm, v, vcnt, nullptr, false, tk);
 }
 
 template <typename T, int L>
 __device__ __forceinline__ void compress_one(const Job& J, uint64_t s, uint64_t gs,
-                                             const Ctl& C, Smem& sm) {
-  if ((s + 1) * blockDim.x * SEG <= J.n) compress_body<T, L, true>(J, s, gs, C, sm);
-  else compress_body<T, L, false>(J, s, gs, C, sm);
+                                             const Ctl& C, Smem& sm, uint32_t& tk) {
+  if ((s + 1) * blockDim.x * SEG <= J.n) compress_body<T, L, true>(J, s, gs, C, sm, tk);
+  else compress_body<T, L, false>(J, s, gs, C, sm, tk);
 }
 
 template <typename T, int L, bool FULL>
@@ -1277,9 +1371,11 @@ __device__ __forceinline__ void decompress_one(const Job& J, uint64_t s, const C
 
 template <int L, bool FULL>
 __device__ __forceinline__ void fused_body(const Job& J, uint64_t s, uint64_t gs, const Ctl& C,
-                                           Smem& sm) {
+                                           Smem& sm, uint32_t& tk) {
   const uint64_t e0 = (s * blockDim.x + threadIdx.x) * SEG;
   const uint32_t vcnt = FULL ? 32u : (e0 >= J.n ? 0u : (uint32_t)min((uint64_t)SEG, J.n - e0));
+  float a[32];
+  load_seg<float>(J.local + (vcnt ? e0 : 0), vcnt, a);  // in flight during the decode
   float v[32];
   FusedSrc fs;
   const bool ok = decode_strip<float, L, FULL>(J, (const uint8_t*)J.in, J.in_bytes, s, C, sm,
@@ -1287,22 +1383,16 @@ __device__ __forceinline__ void fused_body(const Job& J, uint64_t s, uint64_t gs
   fs.pay = (const uint32_t*)((const uint8_t*)J.in + J.pay_off);
   fs.t = sm.t32;
   fs.exists = FULL || (s * blockDim.x + threadIdx.x) / (L / 32) < J.B;
-  __syncthreads();  // every lane has read its payload words
-  const uint64_t s0 = s * blockDim.x * (uint64_t)SEG;
-  strip_to_lds<float>(J.local + s0, FULL ? (uint64_t)blockDim.x * SEG : J.n - s0);
-  __syncthreads();
-  float a[32];
-  lane_from_lds<float>(a);
 #pragma unroll
   for (int i = 0; i < 32; ++i) v[i] = v[i] + a[i];  // incoming + local, fp32
-  encode_strip<float, L, FULL, true>(J, s, gs, C, sm, v, vcnt, &fs, !ok);
+  encode_strip<float, L, FULL, true>(J, s, gs, C, sm, v, vcnt, &fs, !ok, tk);
 }
 
 template <int L>
 __device__ __forceinline__ void fused_one(const Job& J, uint64_t s, uint64_t gs, const Ctl& C,
-                                          Smem& sm) {
-  if ((s + 1) * blockDim.x * SEG <= J.n) fused_body<L, true>(J, s, gs, C, sm);
-  else fused_body<L, false>(J, s, gs, C, sm);
+                                          Smem& sm, uint32_t& tk) {
+  if ((s + 1) * blockDim.x * SEG <= J.n) fused_body<L, true>(J, s, gs, C, sm, tk);
+  else fused_body<L, false>(J, s, gs, C, sm, tk);
 }
 
 // Persistent loop: the next ticket is requested while the current strip is
@@ -1321,6 +1411,22 @@ __device__ __forceinline__ void fused_one(const Job& J, uint64_t s, uint64_t gs,
   }                                                                     \
   epilogue(C);
 
+// Persistent loop of the chained (encoding) operations: BODY sets `nxt`
+// (in thread 0) to the next ticket right after its strip's look-back; a
+// body that never reaches it leaves the exit value.
+#define GZ_CHAIN_LOOP(TOTAL, BODY)                                      \
+  __shared__ Smem sm;                                                   \
+  uint32_t t = first_ticket(C, sm);                                     \
+  while (t < (TOTAL)) {                                                 \
+    uint32_t nxt = 0xFFFFFFFFu;                                         \
+    BODY;                                                               \
+    __syncthreads();                                                    \
+    if (threadIdx.x == 0) sm.cur = nxt;                                 \
+    __syncthreads();                                                    \
+    t = sm.cur;                                                         \
+  }                                                                     \
+  epilogue(C);
+
 #define GZ_KERNEL_ATTR __launch_bounds__(MAX_TPB) __attribute__((amdgpu_waves_per_eu(4, 8)))
 // decode + encode in one pass needs more registers than either alone
 #define GZ_FUSED_ATTR __launch_bounds__(MAX_TPB) __attribute__((amdgpu_waves_per_eu(3, 8)))
@@ -1328,7 +1434,7 @@ __device__ __forceinline__ void fused_one(const Job& J, uint64_t s, uint64_t gs,
 template <typename T, int L>
 __global__ __launch_bounds__(MAX_TPB)
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 3 : 4, 8))) void k_compress(Job J, Ctl C) {
-  GZ_STRIP_LOOP(J.nstrips, (compress_one<T, L>(J, t, t, C, sm)))
+  GZ_CHAIN_LOOP(J.nstrips, (compress_one<T, L>(J, t, t, C, sm, nxt)))
 }
 
 template <typename T, int L>
@@ -1338,7 +1444,7 @@ __global__ GZ_KERNEL_ATTR void k_decompress(Job J, Ctl C) {
 
 template <int L>
 __global__ GZ_FUSED_ATTR void k_fused(Job J, Ctl C) {
-  GZ_STRIP_LOOP(J.nstrips, (fused_one<L>(J, t, t, C, sm)))
+  GZ_CHAIN_LOOP(J.nstrips, (fused_one<L>(J, t, t, C, sm, nxt)))
 }
 
 // Batched: strip_job maps a global strip to its job.  One kernel per
@@ -1347,19 +1453,19 @@ __global__ GZ_FUSED_ATTR void k_fused(Job J, Ctl C) {
 template <uint32_t OP, bool WIDE>
 __device__ __forceinline__ void batch_body(const Job* __restrict__ jobs,
                                            const uint32_t* __restrict__ strip_job, uint32_t t,
-                                           const Ctl& C, Smem& sm) {
+                                           const Ctl& C, Smem& sm, uint32_t& tk) {
   const uint32_t j = strip_job[t];
   const Job J = jobs[j];
   const uint64_t s = t - J.strip0;
   const uint32_t key = (J.dtype << 3) | J.log2L;
   if (OP == 0) {
     switch (key) {
-      case 5: compress_one<float, 32>(J, s, t, C, sm); break;
-      case 6: compress_one<float, 64>(J, s, t, C, sm); break;
-      case 7: compress_one<float, 128>(J, s, t, C, sm); break;
-      case 13: if (WIDE) compress_one<double, 32>(J, s, t, C, sm); break;
-      case 14: if (WIDE) compress_one<double, 64>(J, s, t, C, sm); break;
-      case 15: if (WIDE) compress_one<double, 128>(J, s, t, C, sm); break;
+      case 5: compress_one<float, 32>(J, s, t, C, sm, tk); break;
+      case 6: compress_one<float, 64>(J, s, t, C, sm, tk); break;
+      case 7: compress_one<float, 128>(J, s, t, C, sm, tk); break;
+      case 13: if (WIDE) compress_one<double, 32>(J, s, t, C, sm, tk); break;
+      case 14: if (WIDE) compress_one<double, 64>(J, s, t, C, sm, tk); break;
+      case 15: if (WIDE) compress_one<double, 128>(J, s, t, C, sm, tk); break;
       default: break;
     }
   } else if (OP == 1) {
@@ -1374,9 +1480,9 @@ __device__ __forceinline__ void batch_body(const Job* __restrict__ jobs,
     }
   } else {
     switch (key) {
-      case 5: fused_one<32>(J, s, t, C, sm); break;
-      case 6: fused_one<64>(J, s, t, C, sm); break;
-      case 7: fused_one<128>(J, s, t, C, sm); break;
+      case 5: fused_one<32>(J, s, t, C, sm, tk); break;
+      case 6: fused_one<64>(J, s, t, C, sm, tk); break;
+      case 7: fused_one<128>(J, s, t, C, sm, tk); break;
       default: break;
     }
   }
@@ -1387,7 +1493,11 @@ __global__ __launch_bounds__(MAX_TPB)
 __attribute__((amdgpu_waves_per_eu(OP == 2 || (OP == 0 && WIDE) ? 3 : 4, 8))) void k_batch(const Job* __restrict__ jobs,
                                        const uint32_t* __restrict__ strip_job, uint32_t total,
                                        Ctl C) {
-  GZ_STRIP_LOOP(total, (batch_body<OP, WIDE>(jobs, strip_job, t, C, sm)))
+  if constexpr (OP == 1) {
+    GZ_STRIP_LOOP(total, (batch_body<OP, WIDE>(jobs, strip_job, t, C, sm, nxt)))
+  } else {
+    GZ_CHAIN_LOOP(total, (batch_body<OP, WIDE>(jobs, strip_job, t, C, sm, nxt)))
+  }
 }
 
 // ------------------------------------------------------------ tile mode
@@ -1421,14 +1531,14 @@ __device__ __forceinline__ void store_tile(const Job& J, float* __restrict__ p,
 
 template <bool FULL>
 __device__ __forceinline__ void compress_tiles_body(const Job& J, uint64_t s, uint64_t gs,
-                                                    const Ctl& C, Smem& sm) {
+                                                    const Ctl& C, Smem& sm, uint32_t& tk) {
   const uint64_t seg = s * blockDim.x + threadIdx.x;
   const bool ex = FULL || (seg >> 1) < J.B;
   float v[32];
   load_tile(J, (const float*)J.in + (ex ? seg_first<1>(J, seg) : 0), ex, v);
   LaneCode lc;
   analyze_tile(J, threadIdx.x & 1u, v, ex, sm.wts, lc);
-  emit_strip<float, 64, 1, false, FULL>(J, s, gs, C, sm, ex ? 32u : 0u, lc, nullptr, false);
+  emit_strip<float, 64, 1, false, FULL>(J, s, gs, C, sm, ex ? 32u : 0u, lc, nullptr, false, tk);
 }
 
 __device__ __forceinline__ void load_weights(const Ctl& C, Smem& sm) {
@@ -1441,10 +1551,9 @@ __global__ GZ_FUSED_ATTR void k_compress_tiles(Job J, Ctl C) {
   load_weights(C, sm);
   uint32_t t = first_ticket(C, sm);
   while (t < J.nstrips) {
-    uint32_t nxt = 0;
-    if (threadIdx.x == 0) nxt = atomicAdd(&C.ctrl->ticket, 1u);
-    if ((t + 1) * (uint64_t)blockDim.x <= 2 * J.B) compress_tiles_body<true>(J, t, t, C, sm);
-    else compress_tiles_body<false>(J, t, t, C, sm);
+    uint32_t nxt = 0xFFFFFFFFu;  // the next ticket, taken after the look-back
+    if ((t + 1) * (uint64_t)blockDim.x <= 2 * J.B) compress_tiles_body<true>(J, t, t, C, sm, nxt);
+    else compress_tiles_body<false>(J, t, t, C, sm, nxt);
     __syncthreads();
     if (threadIdx.x == 0) sm.cur = nxt;
     __syncthreads();
