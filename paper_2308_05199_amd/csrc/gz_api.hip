@@ -199,6 +199,38 @@ gz_status stage_upload(gz_ctx* c, const std::vector<Job>& jobs,
   return GZ_OK;
 }
 
+// Ticket order of a batch's strips as (job, strip) pairs.  Jobs that are
+// chains of their own are interleaved round-robin (strip r of every job
+// before strip r + 1 of any), which keeps each chain's in-flight depth
+// small; a chain running through several jobs keeps job order.  Either way
+// a strip's look-back predecessors hold earlier tickets.
+void fill_map(const std::vector<Job>& jobs, bool interleave, std::vector<uint32_t>& map) {
+  uint64_t total = 0;
+  for (const Job& J : jobs) total += J.nstrips;
+  map.resize(2 * total);
+  size_t k = 0;
+  if (!interleave) {
+    for (uint32_t j = 0; j < (uint32_t)jobs.size(); ++j)
+      for (uint64_t r = 0; r < jobs[j].nstrips; ++r) {
+        map[k++] = j;
+        map[k++] = (uint32_t)r;
+      }
+    return;
+  }
+  std::vector<uint32_t> live;
+  for (uint32_t j = 0; j < (uint32_t)jobs.size(); ++j)
+    if (jobs[j].nstrips) live.push_back(j);
+  for (uint64_t r = 0; !live.empty(); ++r) {
+    size_t keep = 0;
+    for (uint32_t j : live) {
+      map[k++] = j;
+      map[k++] = (uint32_t)r;
+      if (r + 1 < jobs[j].nstrips) live[keep++] = j;
+    }
+    live.resize(keep);
+  }
+}
+
 // Builds the jobs of a request batch; fills the strip map.
 gz_status build_requests(gz_ctx* c, gz_op op, const gz_request* r, uint32_t nreq, uint32_t tpb,
                          std::vector<Job>& jobs, std::vector<uint32_t>& map) {
@@ -236,9 +268,7 @@ gz_status build_requests(gz_ctx* c, gz_op op, const gz_request* r, uint32_t nreq
     jobs[j] = J;
   }
   if (strip > c->max_strips || strip >= (1ull << 32)) return GZ_ENOSPC;
-  map.resize(strip);
-  for (uint32_t j = 0; j < nreq; ++j)
-    for (uint64_t s = 0; s < jobs[j].nstrips; ++s) map[jobs[j].strip0 + s] = j;
+  fill_map(jobs, true, map);
   return GZ_OK;
 }
 
@@ -294,10 +324,10 @@ gz_status gz_ctx_create(gz_ctx** out, int device, uint64_t max_elems, uint32_t m
   ok = ok && hipMalloc((void**)&c->jobbase, (size_t)max_requests * 8) == hipSuccess;
   ok = ok && hipMalloc((void**)&c->blob, 1024) == hipSuccess;
   ok = ok && hipMalloc((void**)&c->d_jobs, (size_t)max_requests * sizeof(Job)) == hipSuccess;
-  ok = ok && hipMalloc((void**)&c->d_map, c->max_strips * 4) == hipSuccess;
+  ok = ok && hipMalloc((void**)&c->d_map, c->max_strips * 8) == hipSuccess;
   ok = ok && hipMalloc((void**)&c->train_ws,
                        (size_t)gzs::MLP_MAX_BATCH * gzs::MLP_ROW * sizeof(float)) == hipSuccess;
-  c->stage_bytes = (size_t)max_requests * sizeof(Job) + c->max_strips * 4;
+  c->stage_bytes = (size_t)max_requests * sizeof(Job) + c->max_strips * 8;
   for (int k = 0; ok && k < STAGE_SLOTS; ++k) {
     ok = hipHostMalloc((void**)&c->stage[k], c->stage_bytes, hipHostMallocDefault) == hipSuccess &&
          hipEventCreateWithFlags(&c->stage_ev[k], hipEventDisableTiming) == hipSuccess;
@@ -499,9 +529,8 @@ gz_status gz_scatter_compress(gz_ctx* c, const void* d_root, gz_dtype dtype,
   if (pay > MAX_CHAIN_DW) return GZ_EINVAL;
   if (strip > c->max_strips) return GZ_ENOSPC;
   if (overlaps(d_root, span * esize(dtype), d_out, out_cap)) return GZ_EINVAL;
-  std::vector<uint32_t> map(strip);
-  for (uint32_t j = 0; j < nchunks; ++j)
-    for (uint64_t s = 0; s < jobs[j].nstrips; ++s) map[jobs[j].strip0 + s] = j;
+  std::vector<uint32_t> map;
+  fill_map(jobs, false, map);  // one chain through all chunks
   hipStream_t st = (hipStream_t)stream;
   gz_status r = stage_upload(c, jobs, map, st);
   if (r != GZ_OK) return r;
@@ -542,9 +571,8 @@ gz_status gz_scatter_decompress(gz_ctx* c, const void* d_packed, uint64_t packed
   }
   if (strip > c->max_strips) return GZ_ENOSPC;
   if (overlaps(d_packed, packed_bytes, d_root, span * esize(dtype))) return GZ_EINVAL;
-  std::vector<uint32_t> map(strip);
-  for (uint32_t j = 0; j < nchunks; ++j)
-    for (uint64_t s = 0; s < jobs[j].nstrips; ++s) map[jobs[j].strip0 + s] = j;
+  std::vector<uint32_t> map;
+  fill_map(jobs, true, map);
   hipStream_t st = (hipStream_t)stream;
   gz_status r = stage_upload(c, jobs, map, st);
   if (r != GZ_OK) return r;
@@ -569,8 +597,8 @@ gz_status gz_batch(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t nreq,
   for (const Job& J : jobs) wide = wide || J.dtype == GZ_F64;
   uint64_t g = (p && p->grid) ? p->grid
                               : (uint64_t)c->cus * gzk::occupancy_blocks(3 + (uint32_t)op, wide, 5, tpb);
-  g = std::max<uint64_t>(1, std::min<uint64_t>(g, map.size()));
-  return hip_status(gzk::launch_batch((uint32_t)op, c->d_jobs, c->d_map, (uint32_t)map.size(),
+  g = std::max<uint64_t>(1, std::min<uint64_t>(g, map.size() / 2));
+  return hip_status(gzk::launch_batch((uint32_t)op, c->d_jobs, c->d_map, (uint32_t)(map.size() / 2),
                                       c->ctl(), tpb, (uint32_t)g, wide, st));
 }
 
@@ -588,12 +616,12 @@ gz_status gz_plan_create(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t
   if (!pl) return GZ_ENOMEM;
   pl->ctx = c;
   pl->op = op;
-  pl->total = (uint32_t)map.size();
+  pl->total = (uint32_t)(map.size() / 2);
   pl->tpb = tpb;
   for (const Job& J : jobs) pl->wide = pl->wide || J.dtype == GZ_F64;
   uint64_t g = (p && p->grid) ? p->grid
                               : (uint64_t)c->cus * gzk::occupancy_blocks(3 + (uint32_t)op, pl->wide, 5, tpb);
-  pl->grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(g, map.size()));
+  pl->grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(g, map.size() / 2));
   if (hipMalloc((void**)&pl->d_jobs, jobs.size() * sizeof(Job)) != hipSuccess ||
       hipMalloc((void**)&pl->d_map, map.size() * 4) != hipSuccess) {
     gz_plan_destroy(pl);

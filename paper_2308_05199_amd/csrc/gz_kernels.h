@@ -9,7 +9,8 @@ namespace gzk {
 // op: 0 compress, 1 decompress, 2 fused step (fp32 only)
 hipError_t launch_single(uint32_t op, const Job& J, const Ctl& C, uint32_t tpb, uint32_t grid,
                          hipStream_t st);
-// wide: the batch holds fp64 jobs (larger LDS staging)
+// wide: the batch holds fp64 jobs (larger LDS staging).  d_strip_job: total
+// (job, strip) pairs in ticket order.
 hipError_t launch_batch(uint32_t op, const Job* d_jobs, const uint32_t* d_strip_job,
                         uint32_t total, const Ctl& C, uint32_t tpb, uint32_t grid, bool wide,
                         hipStream_t st);

@@ -1447,25 +1447,27 @@ __global__ GZ_FUSED_ATTR void k_fused(Job J, Ctl C) {
   GZ_CHAIN_LOOP(J.nstrips, (fused_one<L>(J, t, t, C, sm, nxt)))
 }
 
-// Batched: strip_job maps a global strip to its job.  One kernel per
-// operation; WIDE admits fp64 jobs (fp32-only batches avoid the register
-// pressure of the fp64 paths).
+// Batched: ticket t processes strip strip_job[2t + 1] of job strip_job[2t];
+// its look-back word is J.strip0 + that strip.  One kernel per operation;
+// WIDE admits fp64 jobs (fp32-only batches avoid the register pressure of
+// the fp64 paths).
 template <uint32_t OP, bool WIDE>
 __device__ __forceinline__ void batch_body(const Job* __restrict__ jobs,
                                            const uint32_t* __restrict__ strip_job, uint32_t t,
                                            const Ctl& C, Smem& sm, uint32_t& tk) {
-  const uint32_t j = strip_job[t];
+  const uint32_t j = strip_job[2 * (uint64_t)t];
+  const uint64_t s = strip_job[2 * (uint64_t)t + 1];
   const Job J = jobs[j];
-  const uint64_t s = t - J.strip0;
+  const uint64_t gs = J.strip0 + s;
   const uint32_t key = (J.dtype << 3) | J.log2L;
   if (OP == 0) {
     switch (key) {
-      case 5: compress_one<float, 32>(J, s, t, C, sm, tk); break;
-      case 6: compress_one<float, 64>(J, s, t, C, sm, tk); break;
-      case 7: compress_one<float, 128>(J, s, t, C, sm, tk); break;
-      case 13: if (WIDE) compress_one<double, 32>(J, s, t, C, sm, tk); break;
-      case 14: if (WIDE) compress_one<double, 64>(J, s, t, C, sm, tk); break;
-      case 15: if (WIDE) compress_one<double, 128>(J, s, t, C, sm, tk); break;
+      case 5: compress_one<float, 32>(J, s, gs, C, sm, tk); break;
+      case 6: compress_one<float, 64>(J, s, gs, C, sm, tk); break;
+      case 7: compress_one<float, 128>(J, s, gs, C, sm, tk); break;
+      case 13: if (WIDE) compress_one<double, 32>(J, s, gs, C, sm, tk); break;
+      case 14: if (WIDE) compress_one<double, 64>(J, s, gs, C, sm, tk); break;
+      case 15: if (WIDE) compress_one<double, 128>(J, s, gs, C, sm, tk); break;
       default: break;
     }
   } else if (OP == 1) {
@@ -1480,9 +1482,9 @@ __device__ __forceinline__ void batch_body(const Job* __restrict__ jobs,
     }
   } else {
     switch (key) {
-      case 5: fused_one<32>(J, s, t, C, sm, tk); break;
-      case 6: fused_one<64>(J, s, t, C, sm, tk); break;
-      case 7: fused_one<128>(J, s, t, C, sm, tk); break;
+      case 5: fused_one<32>(J, s, gs, C, sm, tk); break;
+      case 6: fused_one<64>(J, s, gs, C, sm, tk); break;
+      case 7: fused_one<128>(J, s, gs, C, sm, tk); break;
       default: break;
     }
   }
