@@ -40,6 +40,7 @@ struct Tuned {
 struct gz_ctx {
   int device = 0;
   int cus = 0;
+  size_t lds_max = 0;  // LDS one workgroup may allocate
   uint64_t max_elems = 0;
   uint32_t max_jobs = 0;
   uint64_t max_strips = 0;
@@ -134,10 +135,19 @@ bool overlaps(const void* a, uint64_t na, const void* b, uint64_t nb) {
   return x < y + nb && y < x + na;
 }
 
+bool tile_mode(const gz_params* p);
+
+// Workgroup size: the caller's, else the tuned one, else the measured
+// default: 512 threads for fp32 1D compression and decompression (half the
+// per-strip ticket, barrier and look-back cost per element), 256 for the
+// fused step (its registers fit three 256-thread workgroups per CU but only
+// one of 512), fp64 and tiles.
 uint32_t pick_tpb(const gz_ctx* c, uint32_t op, uint32_t dt, uint32_t L, const gz_params* p) {
   if (p && p->threads) return p->threads;
   const Tuned& t = c->tuned[op][dt][log2_of(L) - 5];
-  return t.tpb ? t.tpb : 256;
+  if (t.tpb) return t.tpb;
+  const bool wide = op != 2 && dt == GZ_F32 && !tile_mode(p);
+  return wide && gzk::lds_bytes(0, 512) <= c->lds_max ? 512 : 256;
 }
 
 uint32_t pick_grid(const gz_ctx* c, uint32_t op, uint32_t dt, uint32_t L, uint32_t tpb,
@@ -165,11 +175,18 @@ uint32_t pick_tile_grid(const gz_ctx* c, uint32_t op, uint32_t tpb, uint64_t str
   return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(g, strips));
 }
 
+bool tpb_ok(uint32_t t) { return t == 0 || t == 128 || t == 256 || t == 512; }
+
+// The workgroup's LDS fits the device (512-thread fp64 strips may not).
+bool lds_ok(const gz_ctx* c, bool wide, uint32_t tpb) {
+  return gzk::lds_bytes(wide ? 1u : 0u, tpb) <= c->lds_max;
+}
+
 bool params_ok(const gz_params* p, uint32_t& L) {
   L = (p && p->block_len) ? p->block_len : (p && p->mode == 1 ? 64 : 32);
   if (!valid_L(L)) return false;
   if (p) {
-    if (p->threads != 0 && p->threads != 128 && p->threads != 256) return false;
+    if (!tpb_ok(p->threads)) return false;
     if (p->mode > 1) return false;
     if (p->mode == 0 && p->nx != 0) return false;
     if (p->mode == 1 && (L != 64 || p->nx == 0 || p->nx % 8 != 0 || p->select > 2)) return false;
@@ -313,6 +330,11 @@ gz_status gz_ctx_create(gz_ctx** out, int device, uint64_t max_elems, uint32_t m
       wclk_khz <= 0)
     wclk_khz = 100000;
   c->wait_ticks = (uint64_t)wclk_khz * 1000ull;
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess ||
+      lds <= 0)
+    lds = 65536;
+  c->lds_max = (size_t)lds;
   c->max_elems = max_elems;
   c->max_jobs = max_requests;
   // strips of the smallest workgroup (128 lanes = 4096 elements), plus one
@@ -413,6 +435,7 @@ gz_status gz_compress(gz_ctx* c, const void* d_in, uint64_t n, gz_dtype dtype, d
   J.dtype = dtype;
   if (!set_bound(J, dtype, eb)) return GZ_EINVAL;
   const uint32_t tpb = pick_tpb(c, 0, dtype, L, p);
+  if (!lds_ok(c, dtype == GZ_F64, tpb)) return GZ_EUNSUPPORTED;
   set_geom(J, n, L, tpb);
   if (J.nstrips > c->max_strips) return GZ_ENOSPC;
   J.in = d_in;
@@ -443,6 +466,7 @@ gz_status gz_decompress(gz_ctx* c, const void* d_in, uint64_t in_bytes, uint64_t
   memset(&J, 0, sizeof J);
   J.dtype = dtype;
   const uint32_t tpb = pick_tpb(c, 1, dtype, L, p);
+  if (!lds_ok(c, dtype == GZ_F64, tpb)) return GZ_EUNSUPPORTED;
   set_geom(J, n, L, tpb);
   if (J.nstrips > c->max_strips) return GZ_ENOSPC;
   J.in = d_in;
@@ -477,6 +501,7 @@ gz_status gz_fused_reduce_step(gz_ctx* c, const void* d_cmp_in, uint64_t in_byte
   J.dtype = GZ_F32;
   if (!set_bound(J, GZ_F32, eb)) return GZ_EINVAL;
   const uint32_t tpb = pick_tpb(c, 2, GZ_F32, L, p);
+  if (!lds_ok(c, false, tpb)) return GZ_EUNSUPPORTED;
   set_geom(J, n, L, tpb);
   if (J.nstrips > c->max_strips) return GZ_ENOSPC;
   J.in = d_cmp_in;
@@ -499,6 +524,7 @@ gz_status gz_scatter_compress(gz_ctx* c, const void* d_root, gz_dtype dtype,
     return GZ_EINVAL;
   if (nchunks > c->max_jobs) return GZ_ENOSPC;
   const uint32_t tpb = pick_tpb(c, 0, dtype, L, p);
+  if (!lds_ok(c, dtype == GZ_F64, tpb)) return GZ_EUNSUPPORTED;
   std::vector<Job> jobs(nchunks);
   Job proto;
   memset(&proto, 0, sizeof proto);
@@ -550,6 +576,7 @@ gz_status gz_scatter_decompress(gz_ctx* c, const void* d_packed, uint64_t packed
     return GZ_EINVAL;
   if (nchunks > c->max_jobs) return GZ_ENOSPC;
   const uint32_t tpb = pick_tpb(c, 1, dtype, L, p);
+  if (!lds_ok(c, dtype == GZ_F64, tpb)) return GZ_EUNSUPPORTED;
   std::vector<Job> jobs(nchunks);
   uint64_t strip = 0, span = 0;
   for (uint32_t j = 0; j < nchunks; ++j) {
@@ -584,17 +611,21 @@ gz_status gz_scatter_decompress(gz_ctx* c, const void* d_packed, uint64_t packed
 gz_status gz_batch(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t nreq,
                    const gz_params* p, gz_stream_t stream) {
   if (!c || op > GZ_OP_FUSED) return GZ_EINVAL;
-  if (p && p->threads != 0 && p->threads != 128 && p->threads != 256) return GZ_EINVAL;
-  const uint32_t tpb = (p && p->threads) ? p->threads : pick_tpb(c, op, GZ_F32, 32, nullptr);
+  if (p && !tpb_ok(p->threads)) return GZ_EINVAL;
+  if (!h_reqs) return GZ_EINVAL;
+  bool any_f64 = false;
+  for (uint32_t j = 0; j < nreq; ++j) any_f64 = any_f64 || h_reqs[j].dtype == GZ_F64;
+  const uint32_t tpb = pick_tpb(c, op, any_f64 ? GZ_F64 : GZ_F32, 32, p && p->threads ? p : nullptr);
   std::vector<Job> jobs;
   std::vector<uint32_t> map;
   gz_status r = build_requests(c, op, h_reqs, nreq, tpb, jobs, map);
   if (r != GZ_OK) return r;
+  bool wide = false;
+  for (const Job& J : jobs) wide = wide || J.dtype == GZ_F64;
+  if (!lds_ok(c, wide, tpb)) return GZ_EUNSUPPORTED;
   hipStream_t st = (hipStream_t)stream;
   r = stage_upload(c, jobs, map, st);
   if (r != GZ_OK) return r;
-  bool wide = false;
-  for (const Job& J : jobs) wide = wide || J.dtype == GZ_F64;
   uint64_t g = (p && p->grid) ? p->grid
                               : (uint64_t)c->cus * gzk::occupancy_blocks(3 + (uint32_t)op, wide, 5, tpb);
   g = std::max<uint64_t>(1, std::min<uint64_t>(g, map.size() / 2));
@@ -606,8 +637,11 @@ gz_status gz_plan_create(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t
                          const gz_params* p, gz_plan** out) {
   if (!c || !out || op > GZ_OP_FUSED) return GZ_EINVAL;
   *out = nullptr;
-  if (p && p->threads != 0 && p->threads != 128 && p->threads != 256) return GZ_EINVAL;
-  const uint32_t tpb = (p && p->threads) ? p->threads : pick_tpb(c, op, GZ_F32, 32, nullptr);
+  if (p && !tpb_ok(p->threads)) return GZ_EINVAL;
+  if (!h_reqs) return GZ_EINVAL;
+  bool any_f64 = false;
+  for (uint32_t j = 0; j < nreq; ++j) any_f64 = any_f64 || h_reqs[j].dtype == GZ_F64;
+  const uint32_t tpb = pick_tpb(c, op, any_f64 ? GZ_F64 : GZ_F32, 32, p && p->threads ? p : nullptr);
   std::vector<Job> jobs;
   std::vector<uint32_t> map;
   gz_status r = build_requests(c, op, h_reqs, nreq, tpb, jobs, map);
@@ -619,6 +653,10 @@ gz_status gz_plan_create(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t
   pl->total = (uint32_t)(map.size() / 2);
   pl->tpb = tpb;
   for (const Job& J : jobs) pl->wide = pl->wide || J.dtype == GZ_F64;
+  if (!lds_ok(c, pl->wide, tpb)) {
+    gz_plan_destroy(pl);
+    return GZ_EUNSUPPORTED;
+  }
   uint64_t g = (p && p->grid) ? p->grid
                               : (uint64_t)c->cus * gzk::occupancy_blocks(3 + (uint32_t)op, pl->wide, 5, tpb);
   pl->grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(g, map.size() / 2));
@@ -711,7 +749,7 @@ static bool cache_lookup(const char* path, const std::string& key, uint32_t& tpb
     unsigned t, g;
     // entries with a workgroup size or grid the kernels do not take are ignored
     if (sscanf(line, " {\"key\": \"%255[^\"]\", \"tpb\": %u, \"grid\": %u", k, &t, &g) == 3 &&
-        key == k && (t == 128 || t == 256) && g >= 1 && g <= 65536) {
+        key == k && t != 0 && tpb_ok(t) && g >= 1 && g <= 65536) {
       tpb = t;
       grid = g;
       hit = true;
@@ -785,8 +823,9 @@ gz_status gz_tune(gz_ctx* c, gz_dtype dt, uint32_t block_len, uint64_t n, const 
         r = time_op(c, op, x, s, cap, nb, n, dt, L, tpb, grid, st, e0, e1, ms);
       } else {
         float bms = 1e30f;
-        const uint32_t tpbs[2] = {128, 256};
-        for (uint32_t ti = 0; r == GZ_OK && ti < 2; ++ti) {
+        const uint32_t tpbs[3] = {128, 256, 512};
+        for (uint32_t ti = 0; r == GZ_OK && ti < 3; ++ti) {
+          if (!lds_ok(c, dt == GZ_F64, tpbs[ti])) continue;
           const int occ = gzk::occupancy_blocks(op, dt, log2_of(L), tpbs[ti]);
           const uint32_t grids[4] = {(uint32_t)c->cus, 2u * c->cus, (uint32_t)(c->cus * occ),
                                      (uint32_t)(c->cus * occ * 2)};

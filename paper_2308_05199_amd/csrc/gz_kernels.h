@@ -11,6 +11,8 @@ hipError_t launch_single(uint32_t op, const Job& J, const Ctl& C, uint32_t tpb, 
                          hipStream_t st);
 // wide: the batch holds fp64 jobs (larger LDS staging).  d_strip_job: total
 // (job, strip) pairs in ticket order.
+// LDS one workgroup of tpb threads uses (wide: fp64 strips)
+size_t lds_bytes(uint32_t wide, uint32_t tpb);
 hipError_t launch_batch(uint32_t op, const Job* d_jobs, const uint32_t* d_strip_job,
                         uint32_t total, const Ctl& C, uint32_t tpb, uint32_t grid, bool wide,
                         hipStream_t st);

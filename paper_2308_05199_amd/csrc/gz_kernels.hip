@@ -25,14 +25,17 @@ typedef uint32_t u4u __attribute__((ext_vector_type(4), aligned(4)));
 constexpr uint32_t SPIN_LIMIT = 1u << 22;
 constexpr uint64_t VMASK = (1ull << 34) - 1;
 
+// Look-back words and control counters are read and written at system
+// scope (sc0 sc1): such accesses are not served from an XCD's own L2, so a
+// word published by a workgroup on another XCD is seen on the next poll.
 __device__ __forceinline__ void st_agent(unsigned long long* p, unsigned long long v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 __device__ __forceinline__ unsigned long long ld_agent(const unsigned long long* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 __device__ __forceinline__ uint32_t ld_agent32(const uint32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 __device__ __forceinline__ uint64_t sw_pack(uint64_t flag, uint32_t ep, uint64_t v) {
   return (flag << 62) | ((uint64_t)(ep & 0x0FFFFFFFu) << 34) | (v & VMASK);
@@ -629,15 +632,18 @@ __device__ __forceinline__ void unpack_seg(const uint32_t* pw, uint32_t kind, ui
 // (identical on the LPB lanes of a block) and this lane's share of the
 // payload (base, sign word, residual magnitudes).
 struct LaneCode {
-  uint32_t a[32];   // |d| of the lane's 32 elements
+  uint32_t a[32];   // |d| of the lane's 32 elements (rawregs: their fp32 bits)
+  uint32_t rawregs; // RAW block whose fp32 values sit in a[]
   uint32_t sg;      // sign bits
   int32_t base;     // q of the block's first element (lane w == 0)
   uint32_t kind, F, size_dw;
   bool exists;
 };
 
-// Mode 0: 1D blocks of L consecutive elements, L1D prediction.
-template <typename T, int L, bool FULL>
+// Mode 0: 1D blocks of L consecutive elements, L1D prediction.  KEEP (fp32
+// fused step): a block whose quantisation fails keeps its values' bits in
+// a[] for the RAW payload, since they cannot be re-read from memory.
+template <typename T, int L, bool FULL, bool KEEP = false>
 __device__ __forceinline__ void analyze_1d(const Job& J, uint64_t seg, uint32_t w,
                                            const T (&v)[32], uint32_t vcnt, LaneCode& lc) {
   constexpr int LPB = L / 32;
@@ -658,24 +664,32 @@ __device__ __forceinline__ void analyze_1d(const Job& J, uint64_t seg, uint32_t 
       bad |= valid && bi;
     }
   }
-  // residual magnitudes in place (downwards, so a[i-1] still holds q)
   const int32_t base = (int32_t)a[0];
   const int32_t prev = __shfl_up((int32_t)a[31], 1);
+  const uint32_t badb = grp_or<LPB>(bad ? 1u : 0u);
+  const bool rawregs = KEEP && EW == 1 && badb;
   uint32_t sg = 0, orv = 0;
+  if (rawregs) {
+    // a RAW block stores the values themselves: keep their bits at hand
 #pragma unroll
-  for (int i = 31; i >= 0; --i) {
-    const int32_t pq = i ? (int32_t)a[i - 1] : prev;
-    int32_t d = (int32_t)(a[i] - (uint32_t)pq);
-    if (i == 0 && w == 0) d = 0;
-    if (!FULL && i >= (int)vcnt) d = 0;
-    const uint32_t ad = (uint32_t)(d < 0 ? -d : d);
-    a[i] = ad;
-    orv |= ad;
-    sg = __builtin_amdgcn_alignbit(sg, (uint32_t)d, 31);
+    for (int i = 0; i < 32; ++i)
+      a[i] = (FULL || i < (int)vcnt) ? __float_as_uint((float)v[i]) : 0u;
+  } else {
+    // residual magnitudes in place (downwards, so a[i-1] still holds q)
+#pragma unroll
+    for (int i = 31; i >= 0; --i) {
+      const int32_t pq = i ? (int32_t)a[i - 1] : prev;
+      int32_t d = (int32_t)(a[i] - (uint32_t)pq);
+      if (i == 0 && w == 0) d = 0;
+      if (!FULL && i >= (int)vcnt) d = 0;
+      const uint32_t ad = (uint32_t)(d < 0 ? -d : d);
+      a[i] = ad;
+      orv |= ad;
+      sg = __builtin_amdgcn_alignbit(sg, (uint32_t)d, 31);
+    }
   }
   const uint32_t nzb = grp_or<LPB>((base != 0 ? 1u : 0u) | orv);
   orv = grp_or<LPB>(orv);
-  const uint32_t badb = grp_or<LPB>(bad ? 1u : 0u);
 
   const bool exists = FULL || b < J.B;
   const uint32_t m = FULL ? (uint32_t)L
@@ -694,6 +708,7 @@ __device__ __forceinline__ void analyze_1d(const Job& J, uint64_t seg, uint32_t 
     size_dw = 1u + (F ? (F + 1u) * LPB : 0u);
     if (size_dw > raw_dw) { kind = K_RAW; size_dw = raw_dw; F = 0; }
   }
+  lc.rawregs = (exists && rawregs) ? 1u : 0u;
   lc.sg = sg;
   lc.base = base;
   lc.kind = kind;
@@ -891,6 +906,7 @@ __device__ __forceinline__ void analyze_tile(const Job& J, uint32_t w, const flo
   } else if (size_dw > 64) {
     kind = K_RAW; F = 0; size_dw = 64;
   }
+  lc.rawregs = 0;  // RAW tiles re-read their values from the input
   lc.sg = sg;
   lc.base = base;
   lc.kind = kind;
@@ -995,7 +1011,11 @@ __device__ void emit_strip(const Job& J, uint64_t s, uint64_t gs, const Ctl& C, 
     }
   }
   // a separate (not else) branch: the magnitudes are dead before it runs
-  if (kind == K_RAW) {
+  if (FUSED && kind == K_RAW && lc.rawregs) {
+#pragma unroll
+    for (int i = 0; i < 32; ++i)  // unrolled: a[] stays in registers
+      if ((FULL && MODE == 0) || i < (int)vcnt) st[w * 32 + i] = lc.a[i];
+  } else if (kind == K_RAW) {  // blocks too wide to code (rare): re-derive
     if (FUSED) {
       fused_raw_stage<L / 32>(J, *fs, seg, w, vcnt, st);
     } else {
@@ -1084,7 +1104,7 @@ __device__ __forceinline__ void encode_strip(const Job& J, uint64_t s, uint64_t 
                                              const FusedSrc* fs, bool skip, uint32_t& tk) {
   const uint64_t seg = s * blockDim.x + threadIdx.x;
   LaneCode lc;
-  analyze_1d<T, L, FULL>(J, seg, threadIdx.x & (L / 32 - 1), v, vcnt, lc);
+  analyze_1d<T, L, FULL, FUSED>(J, seg, threadIdx.x & (L / 32 - 1), v, vcnt, lc);
   emit_strip<T, L, 0, FUSED, FULL>(J, s, gs, C, sm, vcnt, lc, fs, skip, tk);
 }
 
@@ -1670,6 +1690,8 @@ __global__ void k_reset(Ctl C) {
 static size_t stage_bytes(uint32_t dtype, uint32_t tpb) {
   return 32 + (size_t)tpb * (SEG * (dtype == 0 ? 1 : 2) + 4) * 4;  // padded segment layout
 }
+
+size_t lds_bytes(uint32_t wide, uint32_t tpb) { return stage_bytes(wide, tpb) + sizeof(Smem); }
 
 template <typename T, int L>
 static hipError_t launch_c(const Job& J, const Ctl& C, uint32_t tpb, uint32_t grid,

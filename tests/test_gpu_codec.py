@@ -50,12 +50,24 @@ def assert_ok(ctx):
     assert ctx.device_status() == 0
 
 
+def unless_lds_limited(fn, dt, tpb):
+    """fn() or None where a 512-thread fp64 workgroup needs more LDS than
+    the device gives one workgroup (the library reports GZ_EUNSUPPORTED)."""
+    from paper_2308_05199_amd import gzccl
+    try:
+        return fn()
+    except gzccl.GzError as e:
+        if e.status == gzccl.GZ_EUNSUPPORTED and dt == np.float64 and tpb == 512:
+            return None
+        raise
+
+
 CASES = [(np.float32, 32), (np.float32, 64), (np.float32, 128),
          (np.float64, 32), (np.float64, 64), (np.float64, 128)]
 
 
 @pytest.mark.parametrize("dt,L", CASES)
-@pytest.mark.parametrize("tpb", [128, 256])
+@pytest.mark.parametrize("tpb", [128, 256, 512])
 def test_compress_matches_oracle(ctx, oracle, dt, L, tpb):
     say("compress", dt.__name__, L, tpb)
     g = np.random.default_rng(0)
@@ -63,7 +75,9 @@ def test_compress_matches_oracle(ctx, oracle, dt, L, tpb):
     x = np.concatenate([synth.sinusoids(n - 3000, seed=1).astype(dt),
                         g.uniform(500, 1000, 3000).astype(dt)])
     for eb in (1e-4, 3e-6):
-        got = gpu_stream(ctx, x, eb, block_len=L, threads=tpb)
+        got = unless_lds_limited(lambda: gpu_stream(ctx, x, eb, block_len=L, threads=tpb), dt, tpb)
+        if got is None:
+            pytest.skip("512-thread fp64 staging exceeds this device's LDS per workgroup")
         want = oracle.compress(x, eb, block_len=L)
         assert got.tobytes() == want.tobytes()
     assert_ok(ctx)
@@ -84,7 +98,7 @@ def test_bytes_independent_of_launch_shape(ctx, oracle, grid):
     say("grid", grid)
     x = synth.sinusoids(200_000, seed=2)
     want = oracle.compress(x, 1e-4, block_len=64)
-    for tpb in (128, 256):
+    for tpb in (128, 256, 512):
         got = gpu_stream(ctx, x, 1e-4, block_len=64, threads=tpb, grid=grid)
         assert got.tobytes() == want.tobytes()
     assert_ok(ctx)
@@ -131,9 +145,12 @@ def test_decompress_matches_oracle(ctx, oracle, dt, L):
     x[17] = np.nan
     s = oracle.compress(x, 1e-4, block_len=L)
     want = oracle.decompress(s)
-    for tpb in (128, 256):
-        y = ctx.decompress(dev(s), n, dtype=torch.float32 if dt == np.float32 else torch.float64,
-                           block_len=L, threads=tpb)
+    for tpb in (128, 256, 512):
+        y = unless_lds_limited(lambda: ctx.decompress(
+            dev(s), n, dtype=torch.float32 if dt == np.float32 else torch.float64, block_len=L,
+            threads=tpb), dt, tpb)
+        if y is None:
+            continue
         torch.cuda.synchronize()
         got = y.cpu().numpy()
         assert got.view(np.uint8).tobytes() == want.view(np.uint8).tobytes()
@@ -165,7 +182,7 @@ def test_fused_matches_oracle(ctx, oracle, L):
     eb = 1e-4
     s = oracle.compress(a, eb, block_len=L)
     want = oracle.fused_step(s, b, eb, block_len=L)
-    for tpb in (128, 256):
+    for tpb in (128, 256, 512):
         out, nb = ctx.fused_reduce_step(dev(s), dev(b), eb, block_len=L, threads=tpb)
         torch.cuda.synchronize()
         got = out[:int(nb.item())].cpu().numpy()

@@ -69,7 +69,7 @@ def random_blob(seed):
 
 
 @pytest.mark.parametrize("select", [1, 2, 0])
-@pytest.mark.parametrize("threads", [128, 256])
+@pytest.mark.parametrize("threads", [128, 256, 512])
 def test_tile_compress_matches_oracle(gz, ctx, oracle, select, threads):
     from paper_2308_05199_amd import selector
     say("tiles", select, threads)
