@@ -68,6 +68,7 @@ struct gz_plan {
   Job* d_jobs = nullptr;
   uint32_t* d_map = nullptr;
   uint32_t total = 0;
+  uint32_t njobs = 0;  // uniform batch: the kernels derive (job, strip)
   uint32_t tpb = 0, grid = 0;
   bool wide = false;
 };
@@ -138,15 +139,13 @@ bool overlaps(const void* a, uint64_t na, const void* b, uint64_t nb) {
 bool tile_mode(const gz_params* p);
 
 // Workgroup size: the caller's, else the tuned one, else the measured
-// default: 512 threads for fp32 1D compression and decompression (half the
-// per-strip ticket, barrier and look-back cost per element), 256 for the
-// fused step (its registers fit three 256-thread workgroups per CU but only
-// one of 512), fp64 and tiles.
+// default: 512 threads for fp32 1D operations (half the per-strip ticket,
+// barrier and look-back cost per element), 256 for fp64 and tiles.
 uint32_t pick_tpb(const gz_ctx* c, uint32_t op, uint32_t dt, uint32_t L, const gz_params* p) {
   if (p && p->threads) return p->threads;
   const Tuned& t = c->tuned[op][dt][log2_of(L) - 5];
   if (t.tpb) return t.tpb;
-  const bool wide = op != 2 && dt == GZ_F32 && !tile_mode(p);
+  const bool wide = dt == GZ_F32 && !tile_mode(p);
   return wide && gzk::lds_bytes(0, 512) <= c->lds_max ? 512 : 256;
 }
 
@@ -246,6 +245,14 @@ void fill_map(const std::vector<Job>& jobs, bool interleave, std::vector<uint32_
     }
     live.resize(keep);
   }
+}
+
+// Job count when all jobs have the same number of strips (the kernels then
+// derive a ticket's job and strip from the interleaved order), else 0.
+uint32_t uniform_jobs(const std::vector<Job>& jobs) {
+  for (const Job& J : jobs)
+    if (J.nstrips != jobs[0].nstrips) return 0;
+  return (uint32_t)jobs.size();
 }
 
 // Builds the jobs of a request batch; fills the strip map.
@@ -561,7 +568,7 @@ gz_status gz_scatter_compress(gz_ctx* c, const void* d_root, gz_dtype dtype,
   gz_status r = stage_upload(c, jobs, map, st);
   if (r != GZ_OK) return r;
   const uint32_t grid = pick_grid(c, 0, dtype, L, tpb, strip, p);
-  return hip_status(gzk::launch_batch(0, c->d_jobs, c->d_map, (uint32_t)strip, c->ctl(), tpb,
+  return hip_status(gzk::launch_batch(0, c->d_jobs, c->d_map, 0, (uint32_t)strip, c->ctl(), tpb,
                                       grid, dtype == GZ_F64, st));
 }
 
@@ -604,7 +611,8 @@ gz_status gz_scatter_decompress(gz_ctx* c, const void* d_packed, uint64_t packed
   gz_status r = stage_upload(c, jobs, map, st);
   if (r != GZ_OK) return r;
   const uint32_t grid = pick_grid(c, 1, dtype, L, tpb, strip, p);
-  return hip_status(gzk::launch_batch(1, c->d_jobs, c->d_map, (uint32_t)strip, c->ctl(), tpb,
+  return hip_status(gzk::launch_batch(1, c->d_jobs, c->d_map, uniform_jobs(jobs), (uint32_t)strip,
+                                      c->ctl(), tpb,
                                       grid, dtype == GZ_F64, st));
 }
 
@@ -629,7 +637,8 @@ gz_status gz_batch(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t nreq,
   uint64_t g = (p && p->grid) ? p->grid
                               : (uint64_t)c->cus * gzk::occupancy_blocks(3 + (uint32_t)op, wide, 5, tpb);
   g = std::max<uint64_t>(1, std::min<uint64_t>(g, map.size() / 2));
-  return hip_status(gzk::launch_batch((uint32_t)op, c->d_jobs, c->d_map, (uint32_t)(map.size() / 2),
+  return hip_status(gzk::launch_batch((uint32_t)op, c->d_jobs, c->d_map, uniform_jobs(jobs),
+                                      (uint32_t)(map.size() / 2),
                                       c->ctl(), tpb, (uint32_t)g, wide, st));
 }
 
@@ -651,6 +660,7 @@ gz_status gz_plan_create(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t
   pl->ctx = c;
   pl->op = op;
   pl->total = (uint32_t)(map.size() / 2);
+  pl->njobs = uniform_jobs(jobs);
   pl->tpb = tpb;
   for (const Job& J : jobs) pl->wide = pl->wide || J.dtype == GZ_F64;
   if (!lds_ok(c, pl->wide, tpb)) {
@@ -677,7 +687,8 @@ gz_status gz_plan_create(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t
 
 gz_status gz_plan_launch(gz_plan* pl, gz_stream_t stream) {
   if (!pl) return GZ_EINVAL;
-  return hip_status(gzk::launch_batch(pl->op, pl->d_jobs, pl->d_map, pl->total, pl->ctx->ctl(),
+  return hip_status(gzk::launch_batch(pl->op, pl->d_jobs, pl->d_map, pl->njobs, pl->total,
+                                      pl->ctx->ctl(),
                                       pl->tpb, pl->grid, pl->wide, (hipStream_t)stream));
 }
 

@@ -9,13 +9,14 @@ namespace gzk {
 // op: 0 compress, 1 decompress, 2 fused step (fp32 only)
 hipError_t launch_single(uint32_t op, const Job& J, const Ctl& C, uint32_t tpb, uint32_t grid,
                          hipStream_t st);
-// wide: the batch holds fp64 jobs (larger LDS staging).  d_strip_job: total
-// (job, strip) pairs in ticket order.
 // LDS one workgroup of tpb threads uses (wide: fp64 strips)
 size_t lds_bytes(uint32_t wide, uint32_t tpb);
+// wide: the batch holds fp64 jobs (larger LDS staging).  d_strip_job: total
+// (job, strip) pairs in ticket order, unused when njobs > 0 (njobs jobs of
+// equal strip counts, interleaved round-robin).
 hipError_t launch_batch(uint32_t op, const Job* d_jobs, const uint32_t* d_strip_job,
-                        uint32_t total, const Ctl& C, uint32_t tpb, uint32_t grid, bool wide,
-                        hipStream_t st);
+                        uint32_t njobs, uint32_t total, const Ctl& C, uint32_t tpb,
+                        uint32_t grid, bool wide, hipStream_t st);
 hipError_t launch_quantize(const void* x, uint64_t n, const Job& J, int32_t* q, uint8_t* fail,
                            hipStream_t st);
 // mode 1 (8x8 tiles, fp32): op 0 compress, 1 decompress

@@ -1448,8 +1448,12 @@ __device__ __forceinline__ void fused_one(const Job& J, uint64_t s, uint64_t gs,
   epilogue(C);
 
 #define GZ_KERNEL_ATTR __launch_bounds__(MAX_TPB) __attribute__((amdgpu_waves_per_eu(4, 8)))
-// decode + encode in one pass needs more registers than either alone
-#define GZ_FUSED_ATTR __launch_bounds__(MAX_TPB) __attribute__((amdgpu_waves_per_eu(3, 8)))
+// The fused step is built for four waves per SIMD (a few registers spill):
+// that fits two 512-thread workgroups per CU, which measured faster than
+// three 256-thread ones without spills.
+#define GZ_FUSED_ATTR __launch_bounds__(MAX_TPB) __attribute__((amdgpu_waves_per_eu(4, 8)))
+// tile encoding (selector and three predictors) needs more registers
+#define GZ_TILE_ATTR __launch_bounds__(MAX_TPB) __attribute__((amdgpu_waves_per_eu(3, 8)))
 
 template <typename T, int L>
 __global__ __launch_bounds__(MAX_TPB)
@@ -1467,16 +1471,17 @@ __global__ GZ_FUSED_ATTR void k_fused(Job J, Ctl C) {
   GZ_CHAIN_LOOP(J.nstrips, (fused_one<L>(J, t, t, C, sm, nxt)))
 }
 
-// Batched: ticket t processes strip strip_job[2t + 1] of job strip_job[2t];
-// its look-back word is J.strip0 + that strip.  One kernel per operation;
-// WIDE admits fp64 jobs (fp32-only batches avoid the register pressure of
-// the fp64 paths).
+// Batched: ticket t processes strip strip_job[2t + 1] of job strip_job[2t]
+// or, when every job has the same strip count (njobs > 0, jobs interleaved
+// round-robin), strip t / njobs of job t % njobs; its look-back word is
+// J.strip0 + that strip.  One kernel per operation; WIDE admits fp64 jobs
+// (fp32-only batches avoid the register pressure of the fp64 paths).
 template <uint32_t OP, bool WIDE>
 __device__ __forceinline__ void batch_body(const Job* __restrict__ jobs,
-                                           const uint32_t* __restrict__ strip_job, uint32_t t,
-                                           const Ctl& C, Smem& sm, uint32_t& tk) {
-  const uint32_t j = strip_job[2 * (uint64_t)t];
-  const uint64_t s = strip_job[2 * (uint64_t)t + 1];
+                                           const uint32_t* __restrict__ strip_job, uint32_t njobs,
+                                           uint32_t t, const Ctl& C, Smem& sm, uint32_t& tk) {
+  const uint32_t j = njobs ? t % njobs : strip_job[2 * (uint64_t)t];
+  const uint64_t s = njobs ? t / njobs : strip_job[2 * (uint64_t)t + 1];
   const Job J = jobs[j];
   const uint64_t gs = J.strip0 + s;
   const uint32_t key = (J.dtype << 3) | J.log2L;
@@ -1512,13 +1517,13 @@ __device__ __forceinline__ void batch_body(const Job* __restrict__ jobs,
 
 template <uint32_t OP, bool WIDE>
 __global__ __launch_bounds__(MAX_TPB)
-__attribute__((amdgpu_waves_per_eu(OP == 2 || (OP == 0 && WIDE) ? 3 : 4, 8))) void k_batch(const Job* __restrict__ jobs,
-                                       const uint32_t* __restrict__ strip_job, uint32_t total,
-                                       Ctl C) {
+__attribute__((amdgpu_waves_per_eu((OP == 0 && WIDE) ? 3 : 4, 8))) void k_batch(const Job* __restrict__ jobs,
+                                       const uint32_t* __restrict__ strip_job, uint32_t njobs,
+                                       uint32_t total, Ctl C) {
   if constexpr (OP == 1) {
-    GZ_STRIP_LOOP(total, (batch_body<OP, WIDE>(jobs, strip_job, t, C, sm, nxt)))
+    GZ_STRIP_LOOP(total, (batch_body<OP, WIDE>(jobs, strip_job, njobs, t, C, sm, nxt)))
   } else {
-    GZ_CHAIN_LOOP(total, (batch_body<OP, WIDE>(jobs, strip_job, t, C, sm, nxt)))
+    GZ_CHAIN_LOOP(total, (batch_body<OP, WIDE>(jobs, strip_job, njobs, t, C, sm, nxt)))
   }
 }
 
@@ -1568,7 +1573,7 @@ __device__ __forceinline__ void load_weights(const Ctl& C, Smem& sm) {
   __syncthreads();
 }
 
-__global__ GZ_FUSED_ATTR void k_compress_tiles(Job J, Ctl C) {
+__global__ GZ_TILE_ATTR void k_compress_tiles(Job J, Ctl C) {
   __shared__ Smem sm;
   load_weights(C, sm);
   uint32_t t = first_ticket(C, sm);
@@ -1756,24 +1761,24 @@ static const void* batch_kernel(uint32_t op, bool wide) {
 }
 
 hipError_t launch_batch(uint32_t op, const Job* d_jobs, const uint32_t* d_strip_job,
-                        uint32_t total, const Ctl& C, uint32_t tpb, uint32_t grid, bool wide,
+                        uint32_t njobs, uint32_t total, const Ctl& C, uint32_t tpb, uint32_t grid, bool wide,
                         hipStream_t st) {
   const size_t lds = stage_bytes(wide ? 1 : 0, tpb);
   if (op == 0 && !wide)
     hipLaunchKernelGGL((k_batch<0, false>), dim3(grid), dim3(tpb), lds, st, d_jobs, d_strip_job,
-                       total, C);
+                       njobs, total, C);
   else if (op == 0)
     hipLaunchKernelGGL((k_batch<0, true>), dim3(grid), dim3(tpb), lds, st, d_jobs, d_strip_job,
-                       total, C);
+                       njobs, total, C);
   else if (op == 1 && !wide)
     hipLaunchKernelGGL((k_batch<1, false>), dim3(grid), dim3(tpb), lds, st, d_jobs, d_strip_job,
-                       total, C);
+                       njobs, total, C);
   else if (op == 1)
     hipLaunchKernelGGL((k_batch<1, true>), dim3(grid), dim3(tpb), lds, st, d_jobs, d_strip_job,
-                       total, C);
+                       njobs, total, C);
   else if (op == 2)
     hipLaunchKernelGGL((k_batch<2, false>), dim3(grid), dim3(tpb), lds, st, d_jobs, d_strip_job,
-                       total, C);
+                       njobs, total, C);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
