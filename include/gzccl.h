@@ -71,9 +71,10 @@ typedef struct gz_plan gz_plan;
 typedef struct gz_graph gz_graph;
 
 /* Encoding parameters.  block_len 32|64|128 (0 = 32); threads per workgroup
- * 128|256|512 (0 = tuned/default; a size whose LDS staging exceeds the device's
- * per-workgroup limit gives GZ_EUNSUPPORTED) and grid (persistent workgroups, 0 = default)
- * never change the bytes.  mode 0 = 1D blocks, 1 = 8x8 tiles (block_len 64,
+ * 128|256|512|1024 (0 = tuned/default; 1024 is built for fp32 1D work only, and
+ * it or a size whose LDS staging exceeds the device's per-workgroup limit gives
+ * GZ_EUNSUPPORTED) and grid (persistent workgroups, 0 = default) never change
+ * the bytes.  mode 0 = 1D blocks, 1 = 8x8 tiles (block_len 64,
  * nx = row length, multiple of 8, n a multiple of 8*nx); select (mode 1):
  * 0 = int8 MLP selector, 1 = exhaustive trial, 2 = always L1D. */
 typedef struct {

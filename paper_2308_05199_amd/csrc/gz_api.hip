@@ -138,15 +138,20 @@ bool overlaps(const void* a, uint64_t na, const void* b, uint64_t nb) {
 
 bool tile_mode(const gz_params* p);
 
-// Workgroup size: the caller's, else the tuned one, else the measured
-// default: 512 threads for fp32 1D operations (half the per-strip ticket,
-// barrier and look-back cost per element), 256 for fp64 and tiles.
+// Workgroup size: the caller's, else the tuned one (1D streams), else the
+// measured default.  fp32 1D encoding and the fused step take 1024 threads
+// (a quarter of the per-strip ticket, barrier and look-back cost per element
+// of 256), fp32 decoding 512 (measured faster than 1024), fp64 and tiles 256.
 uint32_t pick_tpb(const gz_ctx* c, uint32_t op, uint32_t dt, uint32_t L, const gz_params* p) {
   if (p && p->threads) return p->threads;
-  const Tuned& t = c->tuned[op][dt][log2_of(L) - 5];
-  if (t.tpb) return t.tpb;
-  const bool wide = dt == GZ_F32 && !tile_mode(p);
-  return wide && gzk::lds_bytes(0, 512) <= c->lds_max ? 512 : 256;
+  if (!tile_mode(p)) {
+    const Tuned& t = c->tuned[op][dt][log2_of(L) - 5];
+    if (t.tpb) return t.tpb;
+  }
+  if (dt != GZ_F32 || tile_mode(p)) return 256;
+  for (uint32_t t = op == 1 ? 512u : 1024u; t > 256; t /= 2)
+    if (gzk::lds_bytes(0, t) <= c->lds_max) return t;
+  return 256;
 }
 
 uint32_t pick_grid(const gz_ctx* c, uint32_t op, uint32_t dt, uint32_t L, uint32_t tpb,
@@ -174,10 +179,12 @@ uint32_t pick_tile_grid(const gz_ctx* c, uint32_t op, uint32_t tpb, uint64_t str
   return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(g, strips));
 }
 
-bool tpb_ok(uint32_t t) { return t == 0 || t == 128 || t == 256 || t == 512; }
+bool tpb_ok(uint32_t t) { return t == 0 || t == 128 || t == 256 || t == 512 || t == 1024; }
 
-// The workgroup's LDS fits the device (512-thread fp64 strips may not).
-bool lds_ok(const gz_ctx* c, bool wide, uint32_t tpb) {
+// The kernel is built for tpb threads (1024 only for fp32 1D kernels) and
+// the workgroup's LDS fits the device (512-thread fp64 strips may not).
+bool tpb_fits(const gz_ctx* c, bool wide, bool tile, uint32_t tpb) {
+  if (tpb > ((wide || tile) ? gzk::MAX_TPB_WIDE : gzk::MAX_TPB)) return false;
   return gzk::lds_bytes(wide ? 1u : 0u, tpb) <= c->lds_max;
 }
 
@@ -442,7 +449,7 @@ gz_status gz_compress(gz_ctx* c, const void* d_in, uint64_t n, gz_dtype dtype, d
   J.dtype = dtype;
   if (!set_bound(J, dtype, eb)) return GZ_EINVAL;
   const uint32_t tpb = pick_tpb(c, 0, dtype, L, p);
-  if (!lds_ok(c, dtype == GZ_F64, tpb)) return GZ_EUNSUPPORTED;
+  if (!tpb_fits(c, dtype == GZ_F64, tile_mode(p), tpb)) return GZ_EUNSUPPORTED;
   set_geom(J, n, L, tpb);
   if (J.nstrips > c->max_strips) return GZ_ENOSPC;
   J.in = d_in;
@@ -473,7 +480,7 @@ gz_status gz_decompress(gz_ctx* c, const void* d_in, uint64_t in_bytes, uint64_t
   memset(&J, 0, sizeof J);
   J.dtype = dtype;
   const uint32_t tpb = pick_tpb(c, 1, dtype, L, p);
-  if (!lds_ok(c, dtype == GZ_F64, tpb)) return GZ_EUNSUPPORTED;
+  if (!tpb_fits(c, dtype == GZ_F64, tile_mode(p), tpb)) return GZ_EUNSUPPORTED;
   set_geom(J, n, L, tpb);
   if (J.nstrips > c->max_strips) return GZ_ENOSPC;
   J.in = d_in;
@@ -508,7 +515,7 @@ gz_status gz_fused_reduce_step(gz_ctx* c, const void* d_cmp_in, uint64_t in_byte
   J.dtype = GZ_F32;
   if (!set_bound(J, GZ_F32, eb)) return GZ_EINVAL;
   const uint32_t tpb = pick_tpb(c, 2, GZ_F32, L, p);
-  if (!lds_ok(c, false, tpb)) return GZ_EUNSUPPORTED;
+  if (!tpb_fits(c, false, false, tpb)) return GZ_EUNSUPPORTED;
   set_geom(J, n, L, tpb);
   if (J.nstrips > c->max_strips) return GZ_ENOSPC;
   J.in = d_cmp_in;
@@ -531,7 +538,7 @@ gz_status gz_scatter_compress(gz_ctx* c, const void* d_root, gz_dtype dtype,
     return GZ_EINVAL;
   if (nchunks > c->max_jobs) return GZ_ENOSPC;
   const uint32_t tpb = pick_tpb(c, 0, dtype, L, p);
-  if (!lds_ok(c, dtype == GZ_F64, tpb)) return GZ_EUNSUPPORTED;
+  if (!tpb_fits(c, dtype == GZ_F64, false, tpb)) return GZ_EUNSUPPORTED;
   std::vector<Job> jobs(nchunks);
   Job proto;
   memset(&proto, 0, sizeof proto);
@@ -583,7 +590,7 @@ gz_status gz_scatter_decompress(gz_ctx* c, const void* d_packed, uint64_t packed
     return GZ_EINVAL;
   if (nchunks > c->max_jobs) return GZ_ENOSPC;
   const uint32_t tpb = pick_tpb(c, 1, dtype, L, p);
-  if (!lds_ok(c, dtype == GZ_F64, tpb)) return GZ_EUNSUPPORTED;
+  if (!tpb_fits(c, dtype == GZ_F64, false, tpb)) return GZ_EUNSUPPORTED;
   std::vector<Job> jobs(nchunks);
   uint64_t strip = 0, span = 0;
   for (uint32_t j = 0; j < nchunks; ++j) {
@@ -630,7 +637,7 @@ gz_status gz_batch(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t nreq,
   if (r != GZ_OK) return r;
   bool wide = false;
   for (const Job& J : jobs) wide = wide || J.dtype == GZ_F64;
-  if (!lds_ok(c, wide, tpb)) return GZ_EUNSUPPORTED;
+  if (!tpb_fits(c, wide, false, tpb)) return GZ_EUNSUPPORTED;
   hipStream_t st = (hipStream_t)stream;
   r = stage_upload(c, jobs, map, st);
   if (r != GZ_OK) return r;
@@ -663,7 +670,7 @@ gz_status gz_plan_create(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t
   pl->njobs = uniform_jobs(jobs);
   pl->tpb = tpb;
   for (const Job& J : jobs) pl->wide = pl->wide || J.dtype == GZ_F64;
-  if (!lds_ok(c, pl->wide, tpb)) {
+  if (!tpb_fits(c, pl->wide, false, tpb)) {
     gz_plan_destroy(pl);
     return GZ_EUNSUPPORTED;
   }
@@ -830,13 +837,13 @@ gz_status gz_tune(gz_ctx* c, gz_dtype dt, uint32_t block_len, uint64_t n, const 
                L, (unsigned long long)n);
       uint32_t tpb = 0, grid = 0;
       float ms = 0;
-      if (cache_lookup(cache_path, keyb, tpb, grid)) {
+      if (cache_lookup(cache_path, keyb, tpb, grid) && tpb_fits(c, dt == GZ_F64, false, tpb)) {
         r = time_op(c, op, x, s, cap, nb, n, dt, L, tpb, grid, st, e0, e1, ms);
       } else {
         float bms = 1e30f;
-        const uint32_t tpbs[3] = {128, 256, 512};
-        for (uint32_t ti = 0; r == GZ_OK && ti < 3; ++ti) {
-          if (!lds_ok(c, dt == GZ_F64, tpbs[ti])) continue;
+        const uint32_t tpbs[4] = {128, 256, 512, 1024};
+        for (uint32_t ti = 0; r == GZ_OK && ti < 4; ++ti) {
+          if (!tpb_fits(c, dt == GZ_F64, false, tpbs[ti])) continue;
           const int occ = gzk::occupancy_blocks(op, dt, log2_of(L), tpbs[ti]);
           const uint32_t grids[4] = {(uint32_t)c->cus, 2u * c->cus, (uint32_t)(c->cus * occ),
                                      (uint32_t)(c->cus * occ * 2)};

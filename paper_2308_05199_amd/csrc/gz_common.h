@@ -7,7 +7,10 @@ namespace gzk {
 constexpr uint32_t SEG = 32;      // elements per lane segment
 constexpr uint32_t SUPER = 4096;  // elements per superblock (one table entry)
 constexpr uint32_t HDR = 64;      // stream header bytes
-constexpr uint32_t MAX_TPB = 512; // largest workgroup the kernels are built for
+// Largest workgroup the kernels are built for: fp32 1D kernels take
+// 1024-thread strips (32768 elements), fp64 and tile kernels 512.
+constexpr uint32_t MAX_TPB = 1024;
+constexpr uint32_t MAX_TPB_WIDE = 512;
 
 enum : uint32_t { K_ZERO = 0, K_L1D = 1, K_NONE = 2, K_L2D = 3, K_RAW = 7 };
 enum : uint32_t { ERRF_CORRUPT = 1u, ERRF_TIMEOUT = 2u };

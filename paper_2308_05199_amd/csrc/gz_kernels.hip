@@ -1447,22 +1447,22 @@ __device__ __forceinline__ void fused_one(const Job& J, uint64_t s, uint64_t gs,
   }                                                                     \
   epilogue(C);
 
-#define GZ_KERNEL_ATTR __launch_bounds__(MAX_TPB) __attribute__((amdgpu_waves_per_eu(4, 8)))
 // The fused step is built for four waves per SIMD (a few registers spill):
-// that fits two 512-thread workgroups per CU, which measured faster than
-// three 256-thread ones without spills.
+// that fits one 1024-thread workgroup per CU, which measured faster than
+// two of 512 or three 256-thread ones without spills.
 #define GZ_FUSED_ATTR __launch_bounds__(MAX_TPB) __attribute__((amdgpu_waves_per_eu(4, 8)))
 // tile encoding (selector and three predictors) needs more registers
-#define GZ_TILE_ATTR __launch_bounds__(MAX_TPB) __attribute__((amdgpu_waves_per_eu(3, 8)))
+#define GZ_TILE_ATTR __launch_bounds__(MAX_TPB_WIDE) __attribute__((amdgpu_waves_per_eu(3, 8)))
 
 template <typename T, int L>
-__global__ __launch_bounds__(MAX_TPB)
+__global__ __launch_bounds__(sizeof(T) == 4 ? MAX_TPB : MAX_TPB_WIDE)
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 3 : 4, 8))) void k_compress(Job J, Ctl C) {
   GZ_CHAIN_LOOP(J.nstrips, (compress_one<T, L>(J, t, t, C, sm, nxt)))
 }
 
 template <typename T, int L>
-__global__ GZ_KERNEL_ATTR void k_decompress(Job J, Ctl C) {
+__global__ __launch_bounds__(sizeof(T) == 4 ? MAX_TPB : MAX_TPB_WIDE)
+__attribute__((amdgpu_waves_per_eu(4, 8))) void k_decompress(Job J, Ctl C) {
   GZ_STRIP_LOOP(J.nstrips, (decompress_one<T, L>(J, t, C, sm)))
 }
 
@@ -1516,7 +1516,7 @@ __device__ __forceinline__ void batch_body(const Job* __restrict__ jobs,
 }
 
 template <uint32_t OP, bool WIDE>
-__global__ __launch_bounds__(MAX_TPB)
+__global__ __launch_bounds__(WIDE ? MAX_TPB_WIDE : MAX_TPB)
 __attribute__((amdgpu_waves_per_eu((OP == 0 && WIDE) ? 3 : 4, 8))) void k_batch(const Job* __restrict__ jobs,
                                        const uint32_t* __restrict__ strip_job, uint32_t njobs,
                                        uint32_t total, Ctl C) {
@@ -1589,7 +1589,8 @@ __global__ GZ_TILE_ATTR void k_compress_tiles(Job J, Ctl C) {
   epilogue(C);
 }
 
-__global__ GZ_KERNEL_ATTR void k_decompress_tiles(Job J, Ctl C) {
+__global__ __launch_bounds__(MAX_TPB_WIDE)
+__attribute__((amdgpu_waves_per_eu(4, 8))) void k_decompress_tiles(Job J, Ctl C) {
   __shared__ Smem sm;
   uint32_t t = first_ticket(C, sm);
   while (t < J.nstrips) {

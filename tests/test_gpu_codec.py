@@ -50,14 +50,15 @@ def assert_ok(ctx):
     assert ctx.device_status() == 0
 
 
-def unless_lds_limited(fn, dt, tpb):
-    """fn() or None where a 512-thread fp64 workgroup needs more LDS than
-    the device gives one workgroup (the library reports GZ_EUNSUPPORTED)."""
+def unless_unsupported(fn, dt, tpb):
+    """fn() or None where the library reports GZ_EUNSUPPORTED for an fp64
+    workgroup size: 1024 threads are built for fp32 only, and 512 fp64
+    threads may need more LDS than the device gives one workgroup."""
     from paper_2308_05199_amd import gzccl
     try:
         return fn()
     except gzccl.GzError as e:
-        if e.status == gzccl.GZ_EUNSUPPORTED and dt == np.float64 and tpb == 512:
+        if e.status == gzccl.GZ_EUNSUPPORTED and dt == np.float64 and tpb >= 512:
             return None
         raise
 
@@ -67,17 +68,17 @@ CASES = [(np.float32, 32), (np.float32, 64), (np.float32, 128),
 
 
 @pytest.mark.parametrize("dt,L", CASES)
-@pytest.mark.parametrize("tpb", [128, 256, 512])
+@pytest.mark.parametrize("tpb", [128, 256, 512, 1024])
 def test_compress_matches_oracle(ctx, oracle, dt, L, tpb):
     say("compress", dt.__name__, L, tpb)
     g = np.random.default_rng(0)
-    n = 5 * 8192 + 777
+    n = 3 * 32768 + 777
     x = np.concatenate([synth.sinusoids(n - 3000, seed=1).astype(dt),
                         g.uniform(500, 1000, 3000).astype(dt)])
     for eb in (1e-4, 3e-6):
-        got = unless_lds_limited(lambda: gpu_stream(ctx, x, eb, block_len=L, threads=tpb), dt, tpb)
+        got = unless_unsupported(lambda: gpu_stream(ctx, x, eb, block_len=L, threads=tpb), dt, tpb)
         if got is None:
-            pytest.skip("512-thread fp64 staging exceeds this device's LDS per workgroup")
+            pytest.skip(f"{tpb}-thread fp64 workgroups are not supported on this device")
         want = oracle.compress(x, eb, block_len=L)
         assert got.tobytes() == want.tobytes()
     assert_ok(ctx)
@@ -98,7 +99,7 @@ def test_bytes_independent_of_launch_shape(ctx, oracle, grid):
     say("grid", grid)
     x = synth.sinusoids(200_000, seed=2)
     want = oracle.compress(x, 1e-4, block_len=64)
-    for tpb in (128, 256, 512):
+    for tpb in (128, 256, 512, 1024):
         got = gpu_stream(ctx, x, 1e-4, block_len=64, threads=tpb, grid=grid)
         assert got.tobytes() == want.tobytes()
     assert_ok(ctx)
@@ -109,9 +110,10 @@ def test_small_and_ragged(ctx, oracle, n):
     say("ragged", n)
     x = synth.sinusoids(max(n, 1), seed=3)[:n]
     for L in (32, 128):
-        got = gpu_stream(ctx, x, 1e-4, block_len=L, threads=128)
         want = oracle.compress(x, 1e-4, block_len=L)
-        assert got.tobytes() == want.tobytes()
+        for tpb in (128, 1024):
+            got = gpu_stream(ctx, x, 1e-4, block_len=L, threads=tpb)
+            assert got.tobytes() == want.tobytes(), tpb
     assert_ok(ctx)
 
 
@@ -139,14 +141,14 @@ def test_decompress_matches_oracle(ctx, oracle, dt, L):
     import torch
     say("decompress", dt.__name__, L)
     g = np.random.default_rng(5)
-    n = 3 * 8192 + 1001
+    n = 3 * 32768 + 1001
     x = np.concatenate([synth.sinusoids(n - 2000, seed=6).astype(dt),
                         g.uniform(500, 1000, 2000).astype(dt)])
     x[17] = np.nan
     s = oracle.compress(x, 1e-4, block_len=L)
     want = oracle.decompress(s)
-    for tpb in (128, 256, 512):
-        y = unless_lds_limited(lambda: ctx.decompress(
+    for tpb in (128, 256, 512, 1024):
+        y = unless_unsupported(lambda: ctx.decompress(
             dev(s), n, dtype=torch.float32 if dt == np.float32 else torch.float64, block_len=L,
             threads=tpb), dt, tpb)
         if y is None:
@@ -176,13 +178,13 @@ def test_round_trip_on_gpu(ctx, oracle):
 def test_fused_matches_oracle(ctx, oracle, L):
     import torch
     say("fused", L)
-    n = 6 * 8192 + 333
+    n = 3 * 32768 + 333
     a = synth.sinusoids(n, seed=8)
     b = np.random.default_rng(9).normal(0, 0.3, n).astype(np.float32)
     eb = 1e-4
     s = oracle.compress(a, eb, block_len=L)
     want = oracle.fused_step(s, b, eb, block_len=L)
-    for tpb in (128, 256, 512):
+    for tpb in (128, 256, 512, 1024):
         out, nb = ctx.fused_reduce_step(dev(s), dev(b), eb, block_len=L, threads=tpb)
         torch.cuda.synchronize()
         got = out[:int(nb.item())].cpu().numpy()
@@ -354,6 +356,7 @@ def test_corrupt_stream_sets_status(ctx, oracle, corrupt):
 
 
 def test_argument_errors(ctx, gz):
+    import ctypes
     import torch
     say("arg errors")
     x = torch.zeros(100, device="cuda")
@@ -367,6 +370,21 @@ def test_argument_errors(ctx, gz):
     with pytest.raises(gz.GzError) as e:
         ctx.compress(x, 1e-3, block_len=48)
     assert e.value.status == gz.GZ_EINVAL
+    with pytest.raises(gz.GzError) as e:
+        ctx.compress(x, 1e-3, threads=384)
+    assert e.value.status == gz.GZ_EINVAL
+    # 1024-thread workgroups are built for fp32 1D kernels only
+    with pytest.raises(gz.GzError) as e:
+        ctx.compress(torch.zeros(100, dtype=torch.float64, device="cuda"), 1e-3, threads=1024)
+    assert e.value.status == gz.GZ_EUNSUPPORTED
+    xt = torch.zeros(64 * 64, device="cuda")
+    cap = gz.bound(xt.numel(), gz.GZ_F32, 64)
+    out = torch.empty(cap, dtype=torch.uint8, device="cuda")
+    nb = torch.zeros(1, dtype=torch.int64, device="cuda")
+    p = gz.gz_params(64, 1024, 0, 1, 2, 64)
+    st = gz.gz_compress(ctx.h, gz._ptr(xt), xt.numel(), gz.GZ_F32, 1e-3, ctypes.byref(p),
+                        gz._ptr(out), cap, gz._ptr(nb), gz._stream(None))
+    assert st == gz.GZ_EUNSUPPORTED
 
 
 def test_quantize_sampled_bit_patterns(ctx, oracle):
