@@ -1394,8 +1394,7 @@ __device__ __forceinline__ void fused_body(const Job& J, uint64_t s, uint64_t gs
                                            Smem& sm, uint32_t& tk) {
   const uint64_t e0 = (s * blockDim.x + threadIdx.x) * SEG;
   const uint32_t vcnt = FULL ? 32u : (e0 >= J.n ? 0u : (uint32_t)min((uint64_t)SEG, J.n - e0));
-  float a[32];
-  load_seg<float>(J.local + (vcnt ? e0 : 0), vcnt, a);  // in flight during the decode
+  const uint64_t s0 = s * blockDim.x * (uint64_t)SEG;
   float v[32];
   FusedSrc fs;
   const bool ok = decode_strip<float, L, FULL>(J, (const uint8_t*)J.in, J.in_bytes, s, C, sm,
@@ -1403,6 +1402,15 @@ __device__ __forceinline__ void fused_body(const Job& J, uint64_t s, uint64_t gs
   fs.pay = (const uint32_t*)((const uint8_t*)J.in + J.pay_off);
   fs.t = sm.t32;
   fs.exists = FULL || (s * blockDim.x + threadIdx.x) / (L / 32) < J.B;
+  // The local addend moves through LDS with coalesced loads once the decode
+  // is done with the LDS.  (Each lane reading its own 32 values would touch
+  // a different 128-byte line in every lane of every load; loading it before
+  // the decode holds 32 more registers across it: both measured slower.)
+  __syncthreads();  // every lane has read its payload words from LDS
+  strip_to_lds<float>(J.local + s0, FULL ? (uint64_t)blockDim.x * SEG : J.n - s0);
+  __syncthreads();
+  float a[32];
+  lane_from_lds<float>(a);
 #pragma unroll
   for (int i = 0; i < 32; ++i) v[i] = v[i] + a[i];  // incoming + local, fp32
   encode_strip<float, L, FULL, true>(J, s, gs, C, sm, v, vcnt, &fs, !ok, tk);
