@@ -222,6 +222,8 @@ __device__ __forceinline__ double from_raw(const uint32_t* src, double) {
 struct Smem {
   uint32_t cur;                  // strip being processed
   uint32_t epoch;
+  uint32_t tp_key;               // decode: 1 + ticket whose table words follow
+  uint32_t tp_t0, tp_t1;
   uint32_t flag;                 // strip error flags
   uint32_t hdr_ok;
   uint32_t hdr_job;              // 1 + job whose stream header was checked
@@ -243,6 +245,7 @@ __device__ __forceinline__ uint32_t first_ticket(const Ctl& C, Smem& sm) {
   if (threadIdx.x == 0) {
     sm.epoch = ld_agent32(&C.ctrl->epoch);
     sm.hdr_job = 0;
+    sm.tp_key = 0;
     sm.cur = atomicAdd(&C.ctrl->ticket, 1u);
   }
   __syncthreads();
@@ -1267,9 +1270,24 @@ __device__ __forceinline__ void unpack_tile(const uint32_t* pw, uint32_t kind, u
 
 // Decodes the lane's segment of strip s of the stream at `in` into v[];
 // returns false (and flags the context) if the strip is malformed.
+// Superblock-table words bounding strip s's payload (0 where the table is
+// absent or the superblock lies past the end).
+__device__ __forceinline__ void table_words(const Job& J, const uint8_t* in, uint64_t in_bytes,
+                                            uint64_t s, uint32_t& T0, uint32_t& T1) {
+  const uint32_t* table = (const uint32_t*)(in + HDR);
+  const uint64_t sb0 = s * (uint64_t)(blockDim.x * SEG / SUPER);
+  const uint64_t sbn = sb0 + blockDim.x * SEG / SUPER;
+  const bool tab_ok = in_bytes >= J.pay_off;
+  T0 = (tab_ok && sb0 < J.NS) ? table[sb0] : 0u;
+  T1 = (tab_ok && sbn < J.NS) ? table[sbn] : 0u;
+}
+
+// pkey (nonzero): the strip's table words may already sit in sm.tp_t0/t1,
+// fetched by thread 0 during the previous strip (when sm.tp_key == pkey).
 template <typename T, int L, bool FULL, int MODE = 0>
 __device__ bool decode_strip(const Job& J, const uint8_t* in, uint64_t in_bytes, uint64_t s,
-                             const Ctl& C, Smem& sm, T (&v)[32], uint32_t vcnt, DecInfo& di) {
+                             const Ctl& C, Smem& sm, T (&v)[32], uint32_t vcnt, DecInfo& di,
+                             uint32_t pkey = 0) {
   constexpr int LPB = L / 32;
   constexpr uint32_t EW = sizeof(T) / 4;
   const int tid = threadIdx.x;
@@ -1284,11 +1302,20 @@ __device__ bool decode_strip(const Job& J, const uint8_t* in, uint64_t in_bytes,
   const uint32_t* table = (const uint32_t*)(in + HDR);
   const uint64_t sb0 = s * (uint64_t)(TPB * SEG / SUPER);
   const uint64_t sbn = sb0 + TPB * SEG / SUPER;
-  const bool tab_ok = in_bytes >= J.pay_off;
-  const uint32_t T0 = (tab_ok && sb0 < J.NS) ? table[sb0] : 0u;
-  const uint32_t T1 = (tab_ok && sbn < J.NS) ? table[sbn] : 0u;
+  uint32_t T0, T1;
+  if (pkey && sm.tp_key == pkey) {
+    T0 = sm.tp_t0;
+    T1 = sm.tp_t1;
+  } else {
+    table_words(J, in, in_bytes, s, T0, T1);
+  }
+  // a lane that starts a superblock checks its table entry below; the word
+  // is read now, with the others, not after the scan
+  const bool exists = FULL || b < J.B;
+  const bool sb_lane = exists && (seg & (SUPER / SEG - 1)) == 0;
+  const uint32_t Tsb = (sb_lane && in_bytes >= J.pay_off) ? table[seg / (SUPER / SEG)] : 0u;
   if (sm.hdr_job != J.job + 1) check_header(J, in, in_bytes, sm);
-  const bool ok = sm.hdr_ok != 0;  // implies tab_ok
+  const bool ok = sm.hdr_ok != 0;  // implies in_bytes >= J.pay_off
   const uint64_t pay_dw = sm.paydw;
   uint64_t E = 0, En = 0;
   if (ok) {
@@ -1300,7 +1327,6 @@ __device__ bool decode_strip(const Job& J, const uint8_t* in, uint64_t in_bytes,
   const uint32_t* S = g_stage + 4;
   if (rng) S = copy_in((const uint32_t*)(in + J.pay_off) + E, P);
 
-  const bool exists = FULL || b < J.B;
   const uint32_t m = FULL ? (uint32_t)L
                           : (exists ? (uint32_t)min((uint64_t)L, J.n - b * (uint64_t)L) : 0u);
   const uint32_t hb = (rng && exists) ? (uint32_t)in[J.hdr_off + b] : 0u;
@@ -1318,8 +1344,7 @@ __device__ bool decode_strip(const Job& J, const uint8_t* in, uint64_t in_bytes,
   const uint32_t excl_lane = strip_scan(w == 0 ? size_dw : 0u, sm, total);
   const uint32_t boff = (w == 0) ? excl_lane : excl_lane - size_dw;
   bool good = rng && hv && total == P;
-  if (good && exists && (seg & (SUPER / SEG - 1)) == 0)
-    good = (uint64_t)table[seg / (SUPER / SEG)] == E + boff;
+  if (good && sb_lane) good = (uint64_t)Tsb == E + boff;
   if (s == 0) good = good && E == 0;
   if (rng && s == J.nstrips - 1 && tid < 4) {
     const uint64_t pb = J.B + tid;
@@ -1387,6 +1412,41 @@ __device__ __forceinline__ void decompress_one(const Job& J, uint64_t s, const C
                                                Smem& sm) {
   if ((s + 1) * blockDim.x * SEG <= J.n) decompress_body<T, L, true>(J, s, C, sm);
   else decompress_body<T, L, false>(J, s, C, sm);
+}
+
+// Single-stream decoding that fetches the next strip's table words (thread 0
+// holds the next ticket, nxt) while this strip unpacks and stores, so that
+// the next strip's payload copy starts at once: one dependent memory round
+// trip per strip instead of two.
+template <typename T, int L, bool FULL>
+__device__ __forceinline__ void decompress_tp_body(const Job& J, uint64_t s, const Ctl& C,
+                                                   Smem& sm, uint32_t nxt) {
+  const uint8_t* in = (const uint8_t*)J.in;
+  const uint64_t e0 = (s * blockDim.x + threadIdx.x) * SEG;
+  const uint32_t vcnt = FULL ? 32u : (e0 >= J.n ? 0u : (uint32_t)min((uint64_t)SEG, J.n - e0));
+  T v[32];
+  DecInfo di;
+  if (decode_strip<T, L, FULL>(J, in, J.in_bytes, s, C, sm, v, vcnt, di, (uint32_t)s + 1u)) {
+    uint32_t p0 = 0, p1 = 0;
+    if (threadIdx.x == 0 && nxt < J.nstrips) table_words(J, in, J.in_bytes, nxt, p0, p1);
+    __syncthreads();  // every lane has read its payload words
+    lane_to_lds<T>(v);
+    __syncthreads();
+    const uint64_t s0 = s * blockDim.x * (uint64_t)SEG;
+    lds_to_strip<T>((T*)J.out + s0, FULL ? (uint64_t)blockDim.x * SEG : J.n - s0);
+    if (threadIdx.x == 0) {  // read by the next strip after the loop's barrier
+      sm.tp_t0 = p0;
+      sm.tp_t1 = p1;
+      sm.tp_key = nxt + 1u;
+    }
+  }
+}
+
+template <typename T, int L>
+__device__ __forceinline__ void decompress_tp_one(const Job& J, uint64_t s, const Ctl& C,
+                                                  Smem& sm, uint32_t nxt) {
+  if ((s + 1) * blockDim.x * SEG <= J.n) decompress_tp_body<T, L, true>(J, s, C, sm, nxt);
+  else decompress_tp_body<T, L, false>(J, s, C, sm, nxt);
 }
 
 template <int L, bool FULL>
@@ -1471,7 +1531,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 3 : 4, 8))) void k_compress(
 template <typename T, int L>
 __global__ __launch_bounds__(sizeof(T) == 4 ? MAX_TPB : MAX_TPB_WIDE)
 __attribute__((amdgpu_waves_per_eu(4, 8))) void k_decompress(Job J, Ctl C) {
-  GZ_STRIP_LOOP(J.nstrips, (decompress_one<T, L>(J, t, C, sm)))
+  GZ_STRIP_LOOP(J.nstrips, (decompress_tp_one<T, L>(J, t, C, sm, nxt)))
 }
 
 template <int L>
