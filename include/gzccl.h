@@ -91,7 +91,8 @@ typedef struct {
  * Decompression: in = stream of in_bytes, out = T[n] (n and dtype and
  * block_len are what the stream must declare).  Fused step: in = fp32
  * stream of n elements, local = fp32[n] addend, out/out_cap/d_out_bytes as
- * for compression. */
+ * for compression.  Accumulate: in = fp32 stream of in_bytes, out = fp32[n]
+ * accumulator updated in place (see gz_decompress_add). */
 typedef struct {
   const void* in;
   const float* local;
@@ -105,7 +106,12 @@ typedef struct {
   uint32_t block_len;
 } gz_request;
 
-typedef enum { GZ_OP_COMPRESS = 0, GZ_OP_DECOMPRESS = 1, GZ_OP_FUSED = 2 } gz_op;
+typedef enum {
+  GZ_OP_COMPRESS = 0,
+  GZ_OP_DECOMPRESS = 1,
+  GZ_OP_FUSED = 2,
+  GZ_OP_ACCUMULATE = 3
+} gz_op;
 
 /* Creates a context on `device` whose workspace covers calls of up to
  * max_elems elements in total and max_requests requests per batch.
@@ -160,6 +166,18 @@ gz_status gz_fused_reduce_step(gz_ctx* ctx, const void* d_cmp_in,
                                void* d_cmp_out, uint64_t out_cap,
                                uint64_t* d_out_bytes, gz_stream_t stream);
 
+/* The reduction after a receive in recursive-doubling gZ-Allreduce (Sec.
+ * 3.3.2): decode the fp32 stream of in_bytes (n elements, block length and
+ * mode 0 as in p) and add it into d_acc in place, d_acc[i] = fl32(decoded[i]
+ * + d_acc[i]), in one kernel that never writes the decoded values.  d_acc
+ * (caller-owned device memory, n floats) must not overlap the stream.  A
+ * malformed or mismatching stream leaves d_acc unchanged and sets
+ * GZ_ECORRUPT on the device; argument errors return GZ_EINVAL with nothing
+ * enqueued; tile mode is GZ_EINVAL. */
+gz_status gz_decompress_add(gz_ctx* ctx, const void* d_in, uint64_t in_bytes,
+                            uint64_t n, const gz_params* p, float* d_acc,
+                            gz_stream_t stream);
+
 /* gZ-Scatter compression (Sec. 3.3.4): chunk j = d_root[h_displs[j] ..
  * + h_counts[j]) is compressed as its own stream; all chunks in one
  * persistent launch, packed back to back into d_out (out_cap >= sum of the
@@ -185,8 +203,9 @@ gz_status gz_scatter_decompress(gz_ctx* ctx, const void* d_packed,
 /* Batched independent requests (fp32 and fp64 mixed, per-request eb and
  * block length) in one persistent launch: the many small compressions that
  * under-use the GPU one by one (Sec. 3.2.2, Sec. 3.3.3 "total compression
- * cost") share one grid.  op selects compress, decompress or fused step;
- * p gives threads/grid only. */
+ * cost") share one grid.  op selects compress, decompress, fused step or
+ * decode-and-accumulate (fp32 only, as gz_decompress_add); p gives
+ * threads/grid only. */
 gz_status gz_batch(gz_ctx* ctx, gz_op op, const gz_request* h_reqs,
                    uint32_t nreq, const gz_params* p, gz_stream_t stream);
 

@@ -142,14 +142,17 @@ bool tile_mode(const gz_params* p);
 // measured default.  fp32 1D encoding and the fused step take 1024 threads
 // (a quarter of the per-strip ticket, barrier and look-back cost per element
 // of 256), fp32 decoding 512 (measured faster than 1024), fp64 and tiles 256.
+// Operations 0-3 as gz_op; decode-and-accumulate (3) shares decoding's tuning.
+uint32_t tune_op(uint32_t op) { return op == 3 ? 1u : op; }
+
 uint32_t pick_tpb(const gz_ctx* c, uint32_t op, uint32_t dt, uint32_t L, const gz_params* p) {
   if (p && p->threads) return p->threads;
   if (!tile_mode(p)) {
-    const Tuned& t = c->tuned[op][dt][log2_of(L) - 5];
+    const Tuned& t = c->tuned[tune_op(op)][dt][log2_of(L) - 5];
     if (t.tpb) return t.tpb;
   }
   if (dt != GZ_F32 || tile_mode(p)) return 256;
-  for (uint32_t t = op == 1 ? 512u : 1024u; t > 256; t /= 2)
+  for (uint32_t t = tune_op(op) == 1 ? 512u : 1024u; t > 256; t /= 2)
     if (gzk::lds_bytes(0, t) <= c->lds_max) return t;
   return 256;
 }
@@ -160,11 +163,11 @@ uint32_t pick_grid(const gz_ctx* c, uint32_t op, uint32_t dt, uint32_t L, uint32
   if (p && p->grid) {
     g = p->grid;
   } else {
-    const Tuned& t = c->tuned[op][dt][log2_of(L) - 5];
-    if (t.grid && t.tpb == tpb) {
+    const Tuned& t = c->tuned[tune_op(op)][dt][log2_of(L) - 5];
+    if (t.grid && t.tpb == tpb && op != 3) {
       g = t.grid;
     } else {
-      int occ = gzk::occupancy_blocks(op, dt, log2_of(L), tpb);
+      int occ = gzk::occupancy_blocks(op == 3 ? gzk::OCC_ACCUM : op, dt, log2_of(L), tpb);
       g = (uint64_t)c->cus * (uint64_t)occ;
     }
   }
@@ -274,7 +277,8 @@ gz_status build_requests(gz_ctx* c, gz_op op, const gz_request* r, uint32_t nreq
     memset(&J, 0, sizeof J);
     const uint32_t L = q.block_len ? q.block_len : 32;
     if (!valid_L(L) || (q.dtype != GZ_F32 && q.dtype != GZ_F64)) return GZ_EINVAL;
-    if (op == GZ_OP_FUSED && q.dtype != GZ_F32) return GZ_EUNSUPPORTED;
+    if ((op == GZ_OP_FUSED || op == GZ_OP_ACCUMULATE) && q.dtype != GZ_F32)
+      return GZ_EUNSUPPORTED;
     if (q.n && (!q.in || !q.out)) return GZ_EINVAL;
     if (q.n * (uint64_t)esize(q.dtype) >= (1ull << 34)) return GZ_EINVAL;
     J.dtype = q.dtype;
@@ -285,7 +289,9 @@ gz_status build_requests(gz_ctx* c, gz_op op, const gz_request* r, uint32_t nreq
     J.in_bytes = q.in_bytes;
     J.job = j;
     set_geom(J, q.n, L, tpb);
-    if (op != GZ_OP_DECOMPRESS) {
+    if (op == GZ_OP_ACCUMULATE) {
+      if (!q.in || overlaps(q.in, q.in_bytes, q.out, q.n * 4)) return GZ_EINVAL;
+    } else if (op != GZ_OP_DECOMPRESS) {
       if (!set_bound(J, q.dtype, q.eb)) return GZ_EINVAL;
       if (q.out_cap < bound_of(q.n, q.dtype, L)) return GZ_ENOSPC;
       if (op == GZ_OP_FUSED && q.n && !q.local) return GZ_EINVAL;
@@ -462,7 +468,7 @@ gz_status gz_compress(gz_ctx* c, const void* d_in, uint64_t n, gz_dtype dtype, d
     J.mode = 1;
     J.nx = p->nx;
     J.select = p->select;
-    const uint32_t grid = pick_tile_grid(c, 6, tpb, J.nstrips, p);
+    const uint32_t grid = pick_tile_grid(c, gzk::OCC_TILE_C, tpb, J.nstrips, p);
     return hip_status(gzk::launch_tiles(0, J, c->ctl(), tpb, grid, (hipStream_t)stream));
   }
   const uint32_t grid = pick_grid(c, 0, dtype, L, tpb, J.nstrips, p);
@@ -491,7 +497,7 @@ gz_status gz_decompress(gz_ctx* c, const void* d_in, uint64_t in_bytes, uint64_t
     if (n % (8ull * p->nx) != 0) return GZ_EINVAL;
     J.mode = 1;
     J.nx = p->nx;
-    const uint32_t grid = pick_tile_grid(c, 7, tpb, J.nstrips, p);
+    const uint32_t grid = pick_tile_grid(c, gzk::OCC_TILE_D, tpb, J.nstrips, p);
     return hip_status(gzk::launch_tiles(1, J, c->ctl(), tpb, grid, (hipStream_t)stream));
   }
   const uint32_t grid = pick_grid(c, 1, dtype, L, tpb, J.nstrips, p);
@@ -525,6 +531,27 @@ gz_status gz_fused_reduce_step(gz_ctx* c, const void* d_cmp_in, uint64_t in_byte
   J.out_bytes = (unsigned long long*)d_out_bytes;
   const uint32_t grid = pick_grid(c, 2, GZ_F32, L, tpb, J.nstrips, p);
   return hip_status(gzk::launch_single(2, J, c->ctl(), tpb, grid, (hipStream_t)stream));
+}
+
+gz_status gz_decompress_add(gz_ctx* c, const void* d_in, uint64_t in_bytes, uint64_t n,
+                            const gz_params* p, float* d_acc, gz_stream_t stream) {
+  uint32_t L;
+  if (!c || !d_in || !params_ok(p, L) || tile_mode(p)) return GZ_EINVAL;
+  if (n && !d_acc) return GZ_EINVAL;
+  if (n * 4ull >= (1ull << 34)) return GZ_EINVAL;
+  if (overlaps(d_in, in_bytes, d_acc, n * 4)) return GZ_EINVAL;
+  Job J;
+  memset(&J, 0, sizeof J);
+  J.dtype = GZ_F32;
+  const uint32_t tpb = pick_tpb(c, 3, GZ_F32, L, p);
+  if (!tpb_fits(c, false, false, tpb)) return GZ_EUNSUPPORTED;
+  set_geom(J, n, L, tpb);
+  if (J.nstrips > c->max_strips) return GZ_ENOSPC;
+  J.in = d_in;
+  J.in_bytes = in_bytes;
+  J.out = d_acc;
+  const uint32_t grid = pick_grid(c, 3, GZ_F32, L, tpb, J.nstrips, p);
+  return hip_status(gzk::launch_single(3, J, c->ctl(), tpb, grid, (hipStream_t)stream));
 }
 
 gz_status gz_scatter_compress(gz_ctx* c, const void* d_root, gz_dtype dtype,
@@ -625,7 +652,7 @@ gz_status gz_scatter_decompress(gz_ctx* c, const void* d_packed, uint64_t packed
 
 gz_status gz_batch(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t nreq,
                    const gz_params* p, gz_stream_t stream) {
-  if (!c || op > GZ_OP_FUSED) return GZ_EINVAL;
+  if (!c || op > GZ_OP_ACCUMULATE) return GZ_EINVAL;
   if (p && !tpb_ok(p->threads)) return GZ_EINVAL;
   if (!h_reqs) return GZ_EINVAL;
   bool any_f64 = false;
@@ -642,7 +669,7 @@ gz_status gz_batch(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t nreq,
   r = stage_upload(c, jobs, map, st);
   if (r != GZ_OK) return r;
   uint64_t g = (p && p->grid) ? p->grid
-                              : (uint64_t)c->cus * gzk::occupancy_blocks(3 + (uint32_t)op, wide, 5, tpb);
+                              : (uint64_t)c->cus * gzk::occupancy_blocks(gzk::OCC_BATCH + (uint32_t)op, wide, 5, tpb);
   g = std::max<uint64_t>(1, std::min<uint64_t>(g, map.size() / 2));
   return hip_status(gzk::launch_batch((uint32_t)op, c->d_jobs, c->d_map, uniform_jobs(jobs),
                                       (uint32_t)(map.size() / 2),
@@ -651,7 +678,7 @@ gz_status gz_batch(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t nreq,
 
 gz_status gz_plan_create(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t nreq,
                          const gz_params* p, gz_plan** out) {
-  if (!c || !out || op > GZ_OP_FUSED) return GZ_EINVAL;
+  if (!c || !out || op > GZ_OP_ACCUMULATE) return GZ_EINVAL;
   *out = nullptr;
   if (p && !tpb_ok(p->threads)) return GZ_EINVAL;
   if (!h_reqs) return GZ_EINVAL;
@@ -675,7 +702,7 @@ gz_status gz_plan_create(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t
     return GZ_EUNSUPPORTED;
   }
   uint64_t g = (p && p->grid) ? p->grid
-                              : (uint64_t)c->cus * gzk::occupancy_blocks(3 + (uint32_t)op, pl->wide, 5, tpb);
+                              : (uint64_t)c->cus * gzk::occupancy_blocks(gzk::OCC_BATCH + (uint32_t)op, pl->wide, 5, tpb);
   pl->grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(g, map.size() / 2));
   if (hipMalloc((void**)&pl->d_jobs, jobs.size() * sizeof(Job)) != hipSuccess ||
       hipMalloc((void**)&pl->d_map, map.size() * 4) != hipSuccess) {

@@ -6,12 +6,13 @@
 
 namespace gzk {
 
-// op: 0 compress, 1 decompress, 2 fused step (fp32 only)
+// op: 0 compress, 1 decompress, 2 fused step, 3 decode-and-accumulate (2, 3:
+// fp32 only)
 hipError_t launch_single(uint32_t op, const Job& J, const Ctl& C, uint32_t tpb, uint32_t grid,
                          hipStream_t st);
 // LDS one workgroup of tpb threads uses (wide: fp64 strips)
 size_t lds_bytes(uint32_t wide, uint32_t tpb);
-// wide: the batch holds fp64 jobs (larger LDS staging).  d_strip_job: total
+// op: as launch_single.  wide: the batch holds fp64 jobs (larger LDS staging).  d_strip_job: total
 // (job, strip) pairs in ticket order, unused when njobs > 0 (njobs jobs of
 // equal strip counts, interleaved round-robin).
 hipError_t launch_batch(uint32_t op, const Job* d_jobs, const uint32_t* d_strip_job,
@@ -26,8 +27,11 @@ hipError_t launch_tile_trial(const Job& J, int8_t* feat, uint32_t* sizes, uint8_
                              hipStream_t st);
 hipError_t launch_fill(void* x, uint64_t n, uint32_t dtype, hipStream_t st);  // tuning input
 hipError_t launch_reset(const Ctl& C, hipStream_t st);
-// resident workgroups per CU of a kernel (op 3 + k = batched op k, dtype 1 = batch with
-// fp64; op 6/7 = tile compress/decompress)
+// Kernels of occupancy_blocks: ops 0-2 as launch_single, OCC_BATCH + k = batched
+// op k (dtype 1: a batch with fp64), tile compress/decompress, single-stream
+// decode-and-accumulate.
+enum : uint32_t { OCC_BATCH = 3, OCC_TILE_C = 7, OCC_TILE_D = 8, OCC_ACCUM = 9 };
+// resident workgroups per CU of a kernel
 int occupancy_blocks(uint32_t op, uint32_t dtype, uint32_t log2L, uint32_t tpb);
 
 }  // namespace gzk

@@ -1414,6 +1414,71 @@ __device__ __forceinline__ void decompress_one(const Job& J, uint64_t s, const C
   else decompress_body<T, L, false>(J, s, C, sm);
 }
 
+// The lane index as a value the compiler cannot see through: addresses
+// derived from it are formed where they are used, not hoisted out of the
+// persistent loop into registers held across a whole strip.
+__device__ __forceinline__ uint32_t opaque_tid() {
+  uint32_t t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
+// Decode-and-accumulate (fp32): acc[i] = fl32(decoded[i] + acc[i]), the
+// reduction that follows each receive in recursive-doubling Allreduce
+// (Sec. 3.3.2), without writing the decoded values to memory.  A whole
+// strip's accumulator is read with coalesced loads issued before the decode,
+// so they are in flight while it runs.  A malformed stream leaves acc as it
+// was (and flags the context).
+template <int L, bool FULL>
+__device__ __forceinline__ void accum_body(const Job& J, uint64_t s, const Ctl& C, Smem& sm) {
+  constexpr uint32_t STR = seg_stride<float>();
+  const uint32_t TPB = blockDim.x;
+  const uint64_t e0 = (s * TPB + threadIdx.x) * SEG;
+  const uint32_t vcnt = FULL ? 32u : (e0 >= J.n ? 0u : (uint32_t)min((uint64_t)SEG, J.n - e0));
+  const uint64_t s0 = s * TPB * (uint64_t)SEG;
+  uint32_t* acc = (uint32_t*)((float*)J.out + s0);
+  u4u old[8];
+  if (FULL) {  // chunk u*TPB + tid of the strip
+    const uint32_t tid = opaque_tid();
+#pragma unroll
+    for (int u = 0; u < 8; ++u) old[u] = ((const u4u*)(acc + 4ull * u * TPB))[tid];
+  }
+  float v[32];
+  DecInfo di;
+  if (!decode_strip<float, L, FULL>(J, (const uint8_t*)J.in, J.in_bytes, s, C, sm, v, vcnt, di))
+    return;
+  __syncthreads();  // every lane has read its payload words
+  lane_to_lds<float>(v);
+  __syncthreads();
+  const uint32_t* buf = g_stage + 4;
+  if (FULL) {
+    const uint32_t tid = opaque_tid();
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const uint32_t k = u * TPB + tid;  // chunk k = segment k/8, words 4*(k%8)..
+      const u4u d = *(const u4u*)(buf + (k / 8) * STR + 4 * (k % 8));
+      u4u y;
+      y.x = __float_as_uint(__uint_as_float(d.x) + __uint_as_float(old[u].x));
+      y.y = __float_as_uint(__uint_as_float(d.y) + __uint_as_float(old[u].y));
+      y.z = __float_as_uint(__uint_as_float(d.z) + __uint_as_float(old[u].z));
+      y.w = __float_as_uint(__uint_as_float(d.w) + __uint_as_float(old[u].w));
+      ((u4u*)(acc + 4ull * u * TPB))[tid] = y;
+    }
+  } else {  // the tail strip: element by element
+    const uint64_t nv = J.n - s0;
+    for (uint32_t i = threadIdx.x; i < nv; i += TPB) {
+      const float d = __uint_as_float(buf[(i / 32) * STR + i % 32]);
+      acc[i] = __float_as_uint(d + __uint_as_float(acc[i]));
+    }
+  }
+}
+
+template <int L>
+__device__ __forceinline__ void accum_one(const Job& J, uint64_t s, const Ctl& C, Smem& sm) {
+  if ((s + 1) * blockDim.x * SEG <= J.n) accum_body<L, true>(J, s, C, sm);
+  else accum_body<L, false>(J, s, C, sm);
+}
+
 // Single-stream decoding that fetches the next strip's table words (thread 0
 // holds the next ticket, nxt) while this strip unpacks and stores, so that
 // the next strip's payload copy starts at once: one dependent memory round
@@ -1535,6 +1600,12 @@ __attribute__((amdgpu_waves_per_eu(4, 8))) void k_decompress(Job J, Ctl C) {
 }
 
 template <int L>
+__global__ __launch_bounds__(MAX_TPB) __attribute__((amdgpu_waves_per_eu(4, 8)))
+void k_accum(Job J, Ctl C) {
+  GZ_STRIP_LOOP(J.nstrips, (accum_one<L>(J, t, C, sm)))
+}
+
+template <int L>
 __global__ GZ_FUSED_ATTR void k_fused(Job J, Ctl C) {
   GZ_CHAIN_LOOP(J.nstrips, (fused_one<L>(J, t, t, C, sm, nxt)))
 }
@@ -1573,11 +1644,18 @@ __device__ __forceinline__ void batch_body(const Job* __restrict__ jobs,
       case 15: if (WIDE) decompress_one<double, 128>(J, s, C, sm); break;
       default: break;
     }
-  } else {
+  } else if (OP == 2) {
     switch (key) {
       case 5: fused_one<32>(J, s, gs, C, sm, tk); break;
       case 6: fused_one<64>(J, s, gs, C, sm, tk); break;
       case 7: fused_one<128>(J, s, gs, C, sm, tk); break;
+      default: break;
+    }
+  } else {
+    switch (key) {
+      case 5: accum_one<32>(J, s, C, sm); break;
+      case 6: accum_one<64>(J, s, C, sm); break;
+      case 7: accum_one<128>(J, s, C, sm); break;
       default: break;
     }
   }
@@ -1588,7 +1666,7 @@ __global__ __launch_bounds__(WIDE ? MAX_TPB_WIDE : MAX_TPB)
 __attribute__((amdgpu_waves_per_eu((OP == 0 && WIDE) ? 3 : 4, 8))) void k_batch(const Job* __restrict__ jobs,
                                        const uint32_t* __restrict__ strip_job, uint32_t njobs,
                                        uint32_t total, Ctl C) {
-  if constexpr (OP == 1) {
+  if constexpr (OP == 1 || OP == 3) {
     GZ_STRIP_LOOP(total, (batch_body<OP, WIDE>(jobs, strip_job, njobs, t, C, sm, nxt)))
   } else {
     GZ_CHAIN_LOOP(total, (batch_body<OP, WIDE>(jobs, strip_job, njobs, t, C, sm, nxt)))
@@ -1782,6 +1860,12 @@ static hipError_t launch_d(const Job& J, const Ctl& C, uint32_t tpb, uint32_t gr
   return hipGetLastError();
 }
 template <int L>
+static hipError_t launch_a(const Job& J, const Ctl& C, uint32_t tpb, uint32_t grid,
+                           hipStream_t st) {
+  hipLaunchKernelGGL((k_accum<L>), dim3(grid), dim3(tpb), stage_bytes(0, tpb), st, J, C);
+  return hipGetLastError();
+}
+template <int L>
 static hipError_t launch_f(const Job& J, const Ctl& C, uint32_t tpb, uint32_t grid,
                            hipStream_t st) {
   hipLaunchKernelGGL((k_fused<L>), dim3(grid), dim3(tpb), stage_bytes(0, tpb), st, J, C);
@@ -1815,6 +1899,12 @@ hipError_t launch_single(uint32_t op, const Job& J, const Ctl& C, uint32_t tpb, 
       case 6: return launch_f<64>(J, C, tpb, grid, st);
       case 7: return launch_f<128>(J, C, tpb, grid, st);
     }
+  } else if (op == 3) {
+    switch (key) {
+      case 5: return launch_a<32>(J, C, tpb, grid, st);
+      case 6: return launch_a<64>(J, C, tpb, grid, st);
+      case 7: return launch_a<128>(J, C, tpb, grid, st);
+    }
   }
   return hipErrorInvalidValue;
 }
@@ -1825,7 +1915,8 @@ static const void* batch_kernel(uint32_t op, bool wide) {
     case 1: return (const void*)k_batch<0, true>;
     case 2: return (const void*)k_batch<1, false>;
     case 3: return (const void*)k_batch<1, true>;
-    default: return (const void*)k_batch<2, false>;
+    case 4: return (const void*)k_batch<2, false>;
+    default: return (const void*)k_batch<3, false>;
   }
 }
 
@@ -1847,6 +1938,9 @@ hipError_t launch_batch(uint32_t op, const Job* d_jobs, const uint32_t* d_strip_
                        njobs, total, C);
   else if (op == 2)
     hipLaunchKernelGGL((k_batch<2, false>), dim3(grid), dim3(tpb), lds, st, d_jobs, d_strip_job,
+                       njobs, total, C);
+  else if (op == 3 && !wide)
+    hipLaunchKernelGGL((k_batch<3, false>), dim3(grid), dim3(tpb), lds, st, d_jobs, d_strip_job,
                        njobs, total, C);
   else
     return hipErrorInvalidValue;
@@ -1928,15 +2022,22 @@ int occupancy_blocks(uint32_t op, uint32_t dtype, uint32_t log2L, uint32_t tpb) 
       case 6: f = (const void*)k_fused<64>; break;
       case 7: f = (const void*)k_fused<128>; break;
     }
-  } else if (op == 6) {
+  } else if (op == OCC_TILE_C) {
     f = (const void*)k_compress_tiles;
-  } else if (op == 7) {
+  } else if (op == OCC_TILE_D) {
     f = (const void*)k_decompress_tiles;
+  } else if (op == OCC_ACCUM) {
+    switch (log2L) {
+      case 5: f = (const void*)k_accum<32>; break;
+      case 6: f = (const void*)k_accum<64>; break;
+      case 7: f = (const void*)k_accum<128>; break;
+    }
   } else {
-    f = batch_kernel(op - 3, dtype != 0);  // op 3/4/5: batched compress/decompress/fused
+    f = batch_kernel(op - OCC_BATCH, dtype != 0);  // batched op (op - OCC_BATCH)
   }
   if (!f) return 1;
-  const size_t lds = stage_bytes(op == 2 || op >= 6 ? 0 : dtype, tpb);
+  const bool f32_only = op == 2 || op >= OCC_BATCH + 2;  // fused, accumulate, tiles
+  const size_t lds = stage_bytes(f32_only ? 0 : dtype, tpb);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, (int)tpb, lds) != hipSuccess || nb < 1)
     nb = 1;
   return nb;

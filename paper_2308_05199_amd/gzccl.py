@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libgzccl.so")
 
 GZ_OK, GZ_EINVAL, GZ_ENOSPC, GZ_ECORRUPT, GZ_EHIP, GZ_ENOMEM, GZ_EUNSUPPORTED, GZ_ETIMEOUT = range(8)
 GZ_F32, GZ_F64 = 0, 1
-GZ_OP_COMPRESS, GZ_OP_DECOMPRESS, GZ_OP_FUSED = 0, 1, 2
+GZ_OP_COMPRESS, GZ_OP_DECOMPRESS, GZ_OP_FUSED, GZ_OP_ACCUMULATE = 0, 1, 2, 3
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run paper_2308_05199_amd/build.py "
@@ -51,6 +51,7 @@ _SIGS = {
     "gz_compress": ([_vp, _vp, _u64, _i32, _dbl, _pp, _vp, _u64, _vp, _vp], _i32),
     "gz_decompress": ([_vp, _vp, _u64, _u64, _i32, _pp, _vp, _vp], _i32),
     "gz_fused_reduce_step": ([_vp, _vp, _u64, _vp, _u64, _dbl, _pp, _vp, _u64, _vp, _vp], _i32),
+    "gz_decompress_add": ([_vp, _vp, _u64, _u64, _pp, _vp, _vp], _i32),
     "gz_scatter_compress": ([_vp, _vp, _i32, _vp, _vp, _u32, _dbl, _pp, _vp, _u64, _vp, _vp, _vp],
                             _i32),
     "gz_scatter_decompress": ([_vp, _vp, _u64, _vp, _i32, _vp, _vp, _u32, _pp, _vp, _vp], _i32),
@@ -188,6 +189,15 @@ class Context:
                                    ctypes.byref(p), _ptr(out), out.numel(), _ptr(out_bytes),
                                    _stream(stream)), "gz_fused_reduce_step")
         return out, out_bytes
+
+    def decompress_add(self, stream_in, acc, block_len=32, in_bytes=None, threads=0, grid=0,
+                       stream=None):
+        """acc (fp32, on the device) += decoded stream, in place."""
+        ib = stream_in.numel() if in_bytes is None else in_bytes
+        p = _params(block_len, threads, grid)
+        check(gz_decompress_add(self.h, _ptr(stream_in), ib, acc.numel(), ctypes.byref(p),
+                                _ptr(acc), _stream(stream)), "gz_decompress_add")
+        return acc
 
     def scatter_compress(self, root, counts, displs, eb, block_len=32, threads=0, grid=0,
                          out=None, stream=None):

@@ -19,7 +19,8 @@ def declared():
 def test_header_declares_the_boundary():
     names = declared()
     for must in ("gz_compress", "gz_decompress", "gz_fused_reduce_step", "gz_scatter_compress",
-                 "gz_batch", "gz_plan_create", "gz_graph_create", "gz_selector_load"):
+                 "gz_decompress_add", "gz_batch", "gz_plan_create", "gz_graph_create",
+                 "gz_selector_load"):
         assert must in names
 
 
@@ -48,6 +49,7 @@ def test_null_context_is_rejected_without_a_gpu():
     assert gzccl.gz_decompress(None, None, 0, 0, 0, None, None, None) == gzccl.GZ_EINVAL
     assert gzccl.gz_fused_reduce_step(None, None, 0, None, 0, 1e-4, None, None, 0, None,
                                       None) == gzccl.GZ_EINVAL
+    assert gzccl.gz_decompress_add(None, None, 0, 0, None, None, None) == gzccl.GZ_EINVAL
     assert gzccl.gz_batch(None, 0, None, 0, None, None) == gzccl.GZ_EINVAL
     assert gzccl.gz_status_str(gzccl.GZ_ECORRUPT) == b"corrupt or mismatching stream"
 
