@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (scales profiler byte counters)")
     ap.add_argument("--extras", default="",
-                    help="comma list of extra measurements: scatter,batch,selector")
+                    help="comma list of extra measurements: scatter,batch,selector,allreduce")
     return ap.parse_args()
 
 
@@ -89,7 +89,7 @@ def headline(ctx, gz, torch, reps=10):
     ctx.decompress(out, n, out=y, in_bytes=cb)
     torch.cuda.synchronize()
     maxerr = float((y.double() - x.double()).abs().max().item())
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     ev[0].record()
     for _ in range(reps):
         ctx.compress(x, 1e-4, out=out, out_bytes=nb)
@@ -97,9 +97,13 @@ def headline(ctx, gz, torch, reps=10):
     for _ in range(reps):
         ctx.decompress(out, n, out=y, in_bytes=cb)
     ev[2].record()
+    for _ in range(reps):  # y += decoded (y grows; the timing does not depend on it)
+        ctx.decompress_add(out, y, in_bytes=cb)
+    ev[3].record()
     torch.cuda.synchronize()
     tc = ev[0].elapsed_time(ev[1]) / reps
     td = ev[1].elapsed_time(ev[2]) / reps
+    ta = ev[2].elapsed_time(ev[3]) / reps
     raw = 4 * n
     res = {
         "workload": "2^28 fp32 sum of 8 sinusoids + N(0,1e-3), eb 1e-4, L 32",
@@ -109,6 +113,8 @@ def headline(ctx, gz, torch, reps=10):
         "compress_hbm_frac": (raw + cb) / tc / 1e6 / HBM_PEAK_GBPS,
         "decompress_ms": td, "decompress_GBps": raw / td / 1e6,
         "decompress_hbm_frac": (raw + cb) / td / 1e6 / HBM_PEAK_GBPS,
+        "accumulate_ms": ta, "accumulate_GBps": raw / ta / 1e6,
+        "accumulate_hbm_frac": (2 * raw + cb) / ta / 1e6 / HBM_PEAK_GBPS,
     }
     del x, y, out
     torch.cuda.empty_cache()
@@ -283,6 +289,92 @@ def extra_selector(ctx, gz, torch):
     return out
 
 
+def extra_allreduce(ctx, gz, torch, bufs_np, eb):
+    """Both compressed Allreduce schedules on the 8 x 256^3 ranks, each one
+    HIP graph: recursive doubling (log2 8 = 3 steps of a batched compression
+    of the whole buffers and a batched decode-and-accumulate) and the ring
+    (the Reduce_scatter graph plus the Allgather's batched decode of all 8
+    chunk streams on every rank).  Inputs are restored before each replay,
+    outside the timed events."""
+    import numpy as np
+    from paper_2308_05199_amd.allreduce import ReDoubAllreduce, RingAllreduce
+    N, n = len(bufs_np), bufs_np[0].size
+    src = [torch.from_numpy(b).cuda() for b in bufs_np]
+    bufs = [b.clone() for b in src]
+    exact = torch.zeros(n, dtype=torch.float64, device="cuda")
+    for b in src:
+        exact += b.double()
+
+    def restore():
+        for b, x in zip(bufs, src):
+            b.copy_(x)
+
+    def graph_ms(run, reps=5):
+        ts = []
+        for _ in range(reps + 1):
+            restore()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            run()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.mean(ts[1:]))
+
+    red = ReDoubAllreduce(ctx, bufs, eb)
+    t_red = graph_ms(red.run)
+    err_red = max(float((b.double() - exact).abs().max()) for b in bufs)
+    # per-launch: compress (whole buffers) and decode-and-accumulate
+    restore()
+    per, sizes = [], []
+    for i, p in enumerate(red.plans):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        p.launch()
+        e1.record()
+        torch.cuda.synchronize()
+        per.append(e0.elapsed_time(e1))
+        if i % 2 == 0:  # the step's compressed sizes
+            sizes.append(red.sizes.cpu().numpy().astype(np.float64))
+    raw = 4.0 * n
+    comp_ms = float(np.mean(per[0::2]))
+    acc_ms = float(np.mean(per[1::2]))
+    comp_alg = float(np.mean([(raw + z).sum() for z in sizes]))
+    acc_alg = float(np.mean([(z + 2 * raw).sum() for z in sizes]))
+    outs = [torch.empty(n, device="cuda") for _ in range(N)]
+    ring = RingAllreduce(ctx, bufs, outs, eb)
+    t_ring = graph_ms(ring.run)
+    err_ring = float((outs[0].double() - exact).abs().max())
+    restore()
+    ring.rs.run()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    ring.gather.launch()
+    e1.record()
+    torch.cuda.synchronize()
+    t_gather = e0.elapsed_time(e1)
+    fin = ring.rs.result()[1].cpu().numpy().astype(np.float64)
+    gather_alg = float(N * (fin.sum() + raw))
+    st = ctx.device_status()
+    del red, ring, outs, bufs, src, exact
+    torch.cuda.empty_cache()
+    return {
+        "workload": "Allreduce of 8 simulated ranks x 256^3 fp32 (the Reduce_scatter ranks), "
+                    "eb = 1e-4 * range, L = 32, one HIP graph each",
+        "redoub_ms": t_red, "redoub_GBps": N * raw / t_red / 1e6,
+        "redoub_compressions": 3 * 8, "redoub_max_err_over_eb": err_red / eb,
+        "redoub_compress_launch_ms": comp_ms,
+        "redoub_compress_hbm_frac": comp_alg / comp_ms / 1e6 / HBM_PEAK_GBPS,
+        "redoub_accumulate_launch_ms": acc_ms,
+        "redoub_accumulate_hbm_frac": acc_alg / acc_ms / 1e6 / HBM_PEAK_GBPS,
+        "ring_ms": t_ring, "ring_GBps": N * raw / t_ring / 1e6,
+        "ring_max_err_over_eb": err_ring / eb,
+        "ring_allgather_launch_ms": t_gather,
+        "ring_allgather_hbm_frac": gather_alg / t_gather / 1e6 / HBM_PEAK_GBPS,
+        "device_status": st,
+    }
+
+
 def cpu_baseline(bufs_np, eb):
     """The oracle, unchanged, on the same reduce-scatter (all 8 chunks,
     8 operations each) on one host core."""
@@ -397,6 +489,9 @@ def main():
     extras = {}
     for name in [e for e in args.extras.split(",") if e]:
         log("extra:", name)
+        if name == "allreduce":
+            extras[name] = extra_allreduce(ctx, gzccl, torch, bufs_np, eb)
+            continue
         extras[name] = {"scatter": extra_scatter, "batch": extra_batch,
                         "selector": extra_selector}[name](ctx, gzccl, torch)
     cpu = None if args.no_cpu else cpu_baseline(bufs_np, eb)
