@@ -522,6 +522,15 @@ __device__ __forceinline__ void strip_to_lds(const T* __restrict__ src, uint64_t
   }
 }
 
+// The lane index as a value the compiler cannot see through: addresses
+// derived from it are formed where they are used, not hoisted out of the
+// persistent loop into registers held across a whole strip.
+__device__ __forceinline__ uint32_t opaque_tid() {
+  uint32_t t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 // Stores the LDS segment layout to dst[0 .. nvalid) with 16-byte stores.
 template <typename T>
 __device__ __forceinline__ void lds_to_strip(T* __restrict__ dst, uint64_t nvalid) {
@@ -531,6 +540,21 @@ __device__ __forceinline__ void lds_to_strip(T* __restrict__ dst, uint64_t nvali
   const uint32_t nch = (uint32_t)min((uint64_t)TPB * SEGW / 4, (vdw + 3) / 4);
   uint32_t* d32 = (uint32_t*)dst;
   const uint32_t* buf = g_stage + 4;
+  if (nvalid == (uint64_t)TPB * SEG) {  // a whole strip: 8 reads in flight, then 8 stores
+    const uint32_t t = opaque_tid();
+#pragma unroll
+    for (uint32_t h = 0; h < SEGW / 4; h += 8) {
+      u4u r[8];
+#pragma unroll
+      for (uint32_t u = 0; u < 8; ++u) {
+        const uint32_t dw = 4 * ((h + u) * TPB + t);
+        r[u] = *(const u4u*)(buf + (dw / SEGW) * STR + dw % SEGW);
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < 8; ++u) ((u4u*)(d32 + 4ull * (h + u) * TPB))[t] = r[u];
+    }
+    return;
+  }
   for (uint32_t k = tid; k < nch; k += TPB) {
     const uint32_t dw = 4 * k;
     const u4u r = *(const u4u*)(buf + (dw / SEGW) * STR + dw % SEGW);
@@ -1412,15 +1436,6 @@ __device__ __forceinline__ void decompress_one(const Job& J, uint64_t s, const C
                                                Smem& sm) {
   if ((s + 1) * blockDim.x * SEG <= J.n) decompress_body<T, L, true>(J, s, C, sm);
   else decompress_body<T, L, false>(J, s, C, sm);
-}
-
-// The lane index as a value the compiler cannot see through: addresses
-// derived from it are formed where they are used, not hoisted out of the
-// persistent loop into registers held across a whole strip.
-__device__ __forceinline__ uint32_t opaque_tid() {
-  uint32_t t = threadIdx.x;
-  asm volatile("" : "+v"(t));
-  return t;
 }
 
 // Decode-and-accumulate (fp32): acc[i] = fl32(decoded[i] + acc[i]), the
