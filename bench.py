@@ -40,8 +40,9 @@ def parse():
     ap.add_argument("--no-headline", action="store_true", help="skip the 1 GiB compress/decompress")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (scales profiler byte counters)")
-    ap.add_argument("--extras", default="",
-                    help="comma list of extra measurements: scatter,batch,selector,allreduce")
+    ap.add_argument("--extras", default="allreduce,accuracy",
+                    help="comma list of extra measurements: scatter,batch,selector,allreduce,"
+                         "accuracy")
     return ap.parse_args()
 
 
@@ -375,6 +376,51 @@ def extra_allreduce(ctx, gz, torch, bufs_np, eb):
     }
 
 
+def extra_accuracy(ctx, gz, torch, nframes=8):
+    """Image stacking (Sec. 4.4 analogue on synthetic frames): the sum of
+    8 frames of 2048^2, scaled to [0, 1] by the largest pixel of all frames
+    (the absolute bounds 1e-4 and 2e-4 are meant for unit-scale images), by
+    ring and recursive-doubling compressed Allreduce; PSNR = 20 log10(range)
+    - 10 log10(MSE) and NRMSE = RMSE / range of the stacked image against the
+    exact (fp64) sum, range = max - min of that sum."""
+    import math
+    from paper_2308_05199_amd.allreduce import ReDoubAllreduce, RingAllreduce
+    fr = device_frames(torch, nframes).view(nframes, -1)
+    fr /= fr.max()
+    n = fr.shape[1]
+    exact = fr.double().sum(0)
+    rng = float(exact.max() - exact.min())
+
+    def metrics(y):
+        mse = float(((y.double() - exact) ** 2).mean())
+        return {"psnr_db": 20 * math.log10(rng) - 10 * math.log10(mse) if mse > 0 else None,
+                "nrmse": math.sqrt(mse) / rng,
+                "max_err_over_eb": None}
+
+    res = {"workload": f"{nframes} frames of 2048^2 fp32 (gradient background + Poisson(50) "
+                       "+ point sources, scaled to [0, 1]), summed by compressed Allreduce",
+           "range": rng}
+    for eb in (1e-4, 2e-4):
+        bufs = [fr[f].clone() for f in range(nframes)]
+        outs = [torch.empty(n, device="cuda") for _ in range(nframes)]
+        RingAllreduce(ctx, bufs, outs, eb).run()
+        torch.cuda.synchronize()
+        m = metrics(outs[0])
+        m["max_err_over_eb"] = float((outs[0].double() - exact).abs().max()) / eb
+        res[f"ring_eb{eb:g}"] = m
+        ReDoubAllreduce(ctx, bufs, eb).run()
+        torch.cuda.synchronize()
+        worst = max(range(nframes), key=lambda i: float((bufs[i].double() - exact).abs().max()))
+        m = metrics(bufs[worst])
+        m["max_err_over_eb"] = float((bufs[worst].double() - exact).abs().max()) / eb
+        res[f"redoub_eb{eb:g}"] = m
+        del bufs, outs
+    res["device_status"] = ctx.device_status()
+    del fr, exact
+    torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline(bufs_np, eb):
     """The oracle, unchanged, on the same reduce-scatter (all 8 chunks,
     8 operations each) on one host core."""
@@ -491,6 +537,9 @@ def main():
         log("extra:", name)
         if name == "allreduce":
             extras[name] = extra_allreduce(ctx, gzccl, torch, bufs_np, eb)
+            continue
+        if name == "accuracy":
+            extras[name] = extra_accuracy(ctx, gzccl, torch)
             continue
         extras[name] = {"scatter": extra_scatter, "batch": extra_batch,
                         "selector": extra_selector}[name](ctx, gzccl, torch)
