@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (scales profiler byte counters)")
     ap.add_argument("--extras", default="allreduce,accuracy",
-                    help="comma list of extra measurements: scatter,batch,selector,allreduce,"
+                    help="comma list of extra measurements (none for no extras): scatter,batch,selector,allreduce,"
                          "accuracy")
     return ap.parse_args()
 
@@ -533,7 +533,7 @@ def main():
     ratio = float(raw_chunk.sum() / sizes.cpu().numpy().sum())
     head = None if args.no_headline else headline(ctx, gzccl, torch)
     extras = {}
-    for name in [e for e in args.extras.split(",") if e]:
+    for name in [e for e in args.extras.split(",") if e and e != "none"]:
         log("extra:", name)
         if name == "allreduce":
             extras[name] = extra_allreduce(ctx, gzccl, torch, bufs_np, eb)
