@@ -668,8 +668,9 @@ struct LaneCode {
 };
 
 // Mode 0: 1D blocks of L consecutive elements, L1D prediction.  KEEP (fp32
-// fused step): a block whose quantisation fails keeps its values' bits in
-// a[] for the RAW payload, since they cannot be re-read from memory.
+// fused step): a block whose quantisation fails puts its values' bits in a[]
+// for the RAW payload, from the lane's LDS segment, where the fused step
+// stored them (they are not in global memory).
 template <typename T, int L, bool FULL, bool KEEP = false>
 __device__ __forceinline__ void analyze_1d(const Job& J, uint64_t seg, uint32_t w,
                                            const T (&v)[32], uint32_t vcnt, LaneCode& lc) {
@@ -697,10 +698,12 @@ __device__ __forceinline__ void analyze_1d(const Job& J, uint64_t seg, uint32_t 
   const bool rawregs = KEEP && EW == 1 && badb;
   uint32_t sg = 0, orv = 0;
   if (rawregs) {
-    // a RAW block stores the values themselves: keep their bits at hand
+    // a RAW block stores the values themselves: the fused step left them in
+    // the lane's own LDS segment (so v[] need not outlive the quantisation)
+    float u[32];
+    lane_from_lds<float>(u);
 #pragma unroll
-    for (int i = 0; i < 32; ++i)
-      a[i] = (FULL || i < (int)vcnt) ? __float_as_uint((float)v[i]) : 0u;
+    for (int i = 0; i < 32; ++i) a[i] = (FULL || i < (int)vcnt) ? __float_as_uint(u[i]) : 0u;
   } else {
     // residual magnitudes in place (downwards, so a[i-1] still holds q)
 #pragma unroll
@@ -1553,6 +1556,7 @@ __device__ __forceinline__ void fused_body(const Job& J, uint64_t s, uint64_t gs
   lane_from_lds<float>(a);
 #pragma unroll
   for (int i = 0; i < 32; ++i) v[i] = v[i] + a[i];  // incoming + local, fp32
+  lane_to_lds<float>(v);  // the sums, for a RAW block (own segment: no barrier)
   encode_strip<float, L, FULL, true>(J, s, gs, C, sm, v, vcnt, &fs, !ok, tk);
 }
 
