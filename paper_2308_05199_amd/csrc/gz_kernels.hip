@@ -452,9 +452,26 @@ __device__ __forceinline__ void put_planes(const uint32_t (&a)[32], uint32_t F, 
 // Magnitudes a[] from planes src[j * stride], j < F (planes >= F are zero).
 __device__ __forceinline__ void get_planes(const uint32_t* src, uint32_t stride, uint32_t F,
                                            uint32_t (&a)[32]) {
+  if (F == 0) {
 #pragma unroll
-  for (int i = 0; i < 32; ++i) a[i] = 0;
-  for (uint32_t g = 0; 8 * g < F; ++g) {
+    for (int i = 0; i < 32; ++i) a[i] = 0;
+    return;
+  }
+  {  // planes 0..7 set byte 0 and clear the rest (no separate clearing pass)
+    const uint32_t nj = min(F, 8u);
+    uint32_t P[8];
+#pragma unroll
+    for (uint32_t j = 0; j < 8; ++j) P[j] = j < nj ? src[j * stride] : 0u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      uint32_t lo = gather4(P[0], P[1], P[2], P[3], (uint32_t)k);
+      uint32_t hi = gather4(P[4], P[5], P[6], P[7], (uint32_t)k);
+      tr8x8(lo, hi);
+#pragma unroll
+      for (int m = 0; m < 8; ++m) a[8 * k + m] = perm(m < 4 ? lo : hi, 0u, 0x0C0C0C04u + (m & 3));
+    }
+  }
+  for (uint32_t g = 1; 8 * g < F; ++g) {
     const uint32_t nj = min(F - 8 * g, 8u);
     uint32_t P[8];
 #pragma unroll
@@ -630,16 +647,14 @@ __device__ __forceinline__ void unpack_seg(const uint32_t* pw, uint32_t kind, ui
       v[i] = (FULL || i < (int)vcnt) ? from_raw(pw + (w * 32 + i) * EW, T()) : (T)0;
     return;
   }
-  if (kind == K_ZERO || !exists) {
-#pragma unroll
-    for (int i = 0; i < 32; ++i) v[i] = (T)0;
-    return;
-  }
-  // L1D
-  const int32_t base = (int32_t)pw[0];
+  // L1D; a ZERO block (or a lane past the end) is an L1D block with base 0
+  // and no planes, which decodes to +0 without a separate clearing pass
+  const bool z = kind == K_ZERO || !exists;
+  const int32_t base = z ? 0 : (int32_t)pw[0];
+  const uint32_t Fz = z ? 0u : F;
   uint32_t a[32];
-  get_planes(pw + 1 + LPB + w, LPB, F, a);
-  const uint32_t sg = F ? pw[1 + w] : 0u;
+  get_planes(pw + 1 + LPB + w, LPB, Fz, a);
+  const uint32_t sg = Fz ? pw[1 + w] : 0u;
   uint32_t acc = 0;
 #pragma unroll
   for (int i = 0; i < 32; ++i) {
