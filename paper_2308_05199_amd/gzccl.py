@@ -193,6 +193,8 @@ class Context:
     def decompress_add(self, stream_in, acc, block_len=32, in_bytes=None, threads=0, grid=0,
                        stream=None):
         """acc (fp32, on the device) += decoded stream, in place."""
+        if acc.dtype != torch.float32 or not acc.is_contiguous() or not acc.is_cuda:
+            raise GzError(GZ_EINVAL, "decompress_add: acc must be a contiguous fp32 device tensor")
         ib = stream_in.numel() if in_bytes is None else in_bytes
         p = _params(block_len, threads, grid)
         check(gz_decompress_add(self.h, _ptr(stream_in), ib, acc.numel(), ctypes.byref(p),
