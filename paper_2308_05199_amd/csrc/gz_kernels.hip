@@ -106,7 +106,9 @@ __device__ __forceinline__ int32_t quant(float x, double rinv, float t, float eb
                                          bool& bad) {
   float r = (float)((double)x * rinv);
   float rr = __builtin_rintf(r);
-  bool inr = fabsf(r) < 536870912.0f;  // false for NaN
+  // |rr| < 2^29 exactly when |r| < 2^29 (floats from 2^23 up are integers,
+  // which rint leaves alone; below, both hold), so r dies here; NaN fails
+  bool inr = fabsf(rr) < 536870912.0f;
   int32_t q = cvt_sat(rr);
   float d = x - rr * t;
   bad = !inr || !(fabsf(d) <= eblo);
