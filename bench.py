@@ -40,9 +40,9 @@ def parse():
     ap.add_argument("--no-headline", action="store_true", help="skip the 1 GiB compress/decompress")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (scales profiler byte counters)")
-    ap.add_argument("--extras", default="allreduce,accuracy",
+    ap.add_argument("--extras", default="allreduce,accuracy,sweep",
                     help="comma list of extra measurements (none for no extras): scatter,batch,selector,allreduce,"
-                         "accuracy")
+                         "accuracy,sweep")
     return ap.parse_args()
 
 
@@ -288,6 +288,54 @@ def extra_selector(ctx, gz, torch):
     out["mlp_speed_vs_exhaustive"] = (out["mlp"]["compress_GBps"] /
                                       out["exhaustive"]["compress_GBps"])
     return out
+
+
+def extra_sweep(gz, torch):
+    """Fig. 3 analogue (Sec. 3.2.2, "GPU time stagnates for small inputs"):
+    compress throughput of one call of n elements (config-1 recipe, eb 1e-4)
+    for n = 2^14 .. 2^28, and of 2^26 elements as 2^26/n requests of n
+    elements in one persistent launch (a plan: one kernel launch)."""
+    import numpy as np
+    N = 1 << 28
+    rng = np.random.default_rng(0)
+    i = torch.arange(N, device="cuda", dtype=torch.float32) / N
+    x = torch.zeros(N, device="cuda", dtype=torch.float32)
+    for _ in range(8):
+        f, a, ph = rng.uniform(1, 64), rng.uniform(0.1, 1), rng.uniform(0, 2 * np.pi)
+        x += a * torch.sin(2 * np.pi * f * i + ph)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    x += 1e-3 * torch.randn(N, device="cuda", generator=g)
+    del i
+    ctx = gz.Context(0, max_elems=N, max_requests=4096)
+    rows = []
+    for lg in range(14, 29, 2):
+        n = 1 << lg
+        cap = gz.bound(n, gz.GZ_F32, 32)
+        out = torch.empty(cap, dtype=torch.uint8, device="cuda")
+        nb = torch.zeros(1, dtype=torch.int64, device="cuda")
+        t1 = _timed(torch, lambda: ctx.compress(x[:n], 1e-4, out=out, out_bytes=nb), reps=10)
+        row = {"n": n, "single_ms": t1, "single_GBps": 4 * n / t1 / 1e6}
+        B = max(1, (1 << 26) // n)
+        if B > 1:
+            outs = torch.empty(B * cap, dtype=torch.uint8, device="cuda")
+            nbs = torch.zeros(B, dtype=torch.int64, device="cuda")
+            items = [{"in": x[j * n:(j + 1) * n], "out": outs[j * cap:(j + 1) * cap],
+                      "out_bytes": nbs[j:j + 1], "n": n, "out_cap": cap, "eb": 1e-4,
+                      "dtype": gz.GZ_F32, "block_len": 32} for j in range(B)]
+            plan = ctx.plan(gz.GZ_OP_COMPRESS, ctx.requests(items))
+            t2 = _timed(torch, plan.launch, reps=10)
+            row.update({"batch_requests": B, "batch_ms": t2,
+                        "batch_GBps": 4 * B * n / t2 / 1e6})
+            plan.close()
+            del outs, nbs
+        rows.append(row)
+    st = ctx.device_status()
+    ctx.close()
+    del x
+    torch.cuda.empty_cache()
+    return {"workload": "config-1 recipe, eb 1e-4, L 32: one call of n elements vs 2^26/n "
+                        "requests of n in one launch", "points": rows, "device_status": st}
 
 
 def extra_allreduce(ctx, gz, torch, bufs_np, eb):
@@ -540,6 +588,9 @@ def main():
             continue
         if name == "accuracy":
             extras[name] = extra_accuracy(ctx, gzccl, torch)
+            continue
+        if name == "sweep":
+            extras[name] = extra_sweep(gzccl, torch)
             continue
         extras[name] = {"scatter": extra_scatter, "batch": extra_batch,
                         "selector": extra_selector}[name](ctx, gzccl, torch)
