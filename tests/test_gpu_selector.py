@@ -151,3 +151,89 @@ def test_adam_step_matches_formula(gz, ctx):
     v = 0.001 * gr.astype(np.float64) ** 2
     want = w - 1e-2 * (m / 0.1) / (np.sqrt(v / 0.001) + 1e-8)
     assert np.allclose(W.cpu().numpy(), want, rtol=1e-5, atol=1e-6)
+
+
+def _device_grf(torch, shape, seed, slope=-3.0):
+    """The GRF recipe (P(k) ~ k^-3, k = 0 removed, mean 0, std 1) on the
+    device with torch.fft, so that the 512M-element workload needs no host
+    generation."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    spec = torch.fft.rfftn(torch.randn(shape, device="cuda", generator=g))
+    k2 = torch.zeros(spec.shape, device="cuda")
+    for ax, n in enumerate(shape):
+        fr = torch.fft.rfftfreq(n, device="cuda") if ax == len(shape) - 1 else \
+            torch.fft.fftfreq(n, device="cuda")
+        sh = [1] * len(shape)
+        sh[ax] = fr.numel()
+        k2 = k2 + fr.view(sh) ** 2
+    k2[0, 0, 0] = 1.0
+    amp = k2 ** (slope / 4.0)
+    amp[0, 0, 0] = 0.0
+    f = torch.fft.irfftn(spec * amp, s=shape)
+    return ((f - f.mean()) / f.std()).float().reshape(-1)
+
+
+def test_config4_full_size_sampled(gz, oracle):
+    """512M fp32 elements of mixed fields (10 GRFs of 256^3 as 256-wide rows,
+    40 noisy 2048^2 images, a 50%-zero sparse array as 8-wide rows) in tile
+    mode with the int8 selector: windows of 64 rows of every kind of field
+    decode bit for bit like the oracle's stream of the window (tiles, their
+    kinds and their payloads depend only on the tile), with the same header
+    bytes, and every element is within eb."""
+    import ctypes
+    import torch
+    sys.path.insert(0, __import__("os").path.dirname(__import__("os").path.dirname(
+        __import__("os").path.abspath(__file__))))
+    from bench import device_frames
+    from paper_2308_05199_amd import selector
+    say("config 4 full size")
+    ctx = gz.Context(0, max_elems=1 << 28, max_requests=64)
+    blob = random_blob(11)
+    selector.load(ctx, blob)
+    fields = [(_device_grf(torch, (256, 256, 256), 100 + k), 256) for k in range(10)]
+    imgs = device_frames(torch, 40, seed=3).view(40, -1)
+    fields += [(imgs[k], 2048) for k in range(40)]
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    ns = 201 * (1 << 20)  # brings the total to over 2^29
+    sp = torch.randn(ns, device="cuda", generator=g) * (torch.rand(ns, device="cuda",
+                                                                   generator=g) < 0.5)
+    fields.append((sp, 8))
+    total = sum(f.numel() for f, _ in fields)
+    assert total >= 512 * (1 << 20)
+    say("fields ready", total)
+    rng = np.random.default_rng(1)
+    checked = 0
+    for idx, (x, nx) in enumerate(fields):
+        n = x.numel()
+        eb = 1e-4 * float(x.max() - x.min())
+        cap = gz.bound(n, gz.GZ_F32, 64)
+        out = torch.empty(cap, dtype=torch.uint8, device="cuda")
+        nb = torch.zeros(1, dtype=torch.int64, device="cuda")
+        p = tile_params(gz, nx, 0)
+        gz.check(gz.gz_compress(ctx.h, gz._ptr(x), n, gz.GZ_F32, eb, ctypes.byref(p),
+                                gz._ptr(out), cap, gz._ptr(nb), gz._stream(None)), "tiles")
+        y = torch.empty(n, device="cuda")
+        gz.check(gz.gz_decompress(ctx.h, gz._ptr(out), int(nb.item()), n, gz.GZ_F32,
+                                  ctypes.byref(p), gz._ptr(y), gz._stream(None)), "untile")
+        torch.cuda.synchronize()
+        assert float((y.double() - x.double()).abs().max()) <= eb, idx
+        if idx % 5 and idx != len(fields) - 1:
+            continue  # windows of every fifth field and of the sparse array
+        rows = n // nx
+        NS = -(-n // 4096)
+        hoff = 64 + 4 * NS
+        heads = out[hoff:hoff + n // 64].cpu().numpy()
+        for r0 in [int(v) * 8 for v in rng.integers(0, rows // 8 - 8, 2)] + [rows - 64]:
+            lo, hi = r0 * nx, (r0 + 64) * nx
+            xw = x[lo:hi].cpu().numpy()
+            s = oracle.compress(xw, eb, block_len=64, mode=1, nx=nx, select=0, blob=blob)
+            want = oracle.decompress(s)
+            assert y[lo:hi].cpu().numpy().tobytes() == want.tobytes(), (idx, r0)
+            whoff = 64 + 4 * (-(-xw.size // 4096))
+            assert heads[lo // 64:hi // 64].tobytes() == s[whoff:whoff + xw.size // 64].tobytes()
+            checked += 1
+    say("windows checked", checked)
+    assert ctx.device_status() == 0
+    ctx.close()
