@@ -161,3 +161,64 @@ def test_tuner_keeps_bytes(gz, ctx, oracle, tmp_path):
     torch.cuda.synchronize()
     want = oracle.compress(x, 1e-4, block_len=best.block_len)
     assert out[:int(nb.item())].cpu().numpy().tobytes() == want.tobytes()
+
+
+def test_batch_config5_full(gz, oracle):
+    """The full batched workload: 4096 requests, log-uniform 4 KiB - 16 MiB
+    (~8 GB), fp32/fp64, eb log-uniform in [1e-6, 1e-2], GRF-like or image-like
+    rows generated on the device, block lengths 32/64/128; one persistent
+    launch each way.  Every request decodes within its eb; every 128th
+    request's bytes and decoded values equal the oracle's."""
+    import torch
+    say("batch config 5 full")
+    reqs = synth.mixed_requests(4096, seed=0, lo_bytes=4096, hi_bytes=16 << 20)
+    ctx = gz.Context(0, max_elems=sum(r["n"] for r in reqs) + 1, max_requests=4096)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    ins, outs, nbs, items = [], [], [], []
+    for i, r in enumerate(reqs):
+        dt = torch.float32 if r["dtype"] == np.float32 else torch.float64
+        n = r["n"]
+        if r["kind"] == "grf":   # smooth random walk, unit variance
+            x = torch.cumsum(torch.randn(n, device="cuda", generator=g, dtype=torch.float64), 0)
+            x = (x - x.mean()) / x.std().clamp_min(1e-30)
+        else:                    # image-like row: level + Poisson(50)
+            base = 100 + 100 * torch.rand(1, device="cuda", generator=g, dtype=torch.float64)
+            x = (base + torch.poisson(torch.full((n,), 50.0, device="cuda", dtype=torch.float64),
+                                      generator=g)) / 100
+        x = x.to(dt)
+        code = gz.GZ_F32 if dt == torch.float32 else gz.GZ_F64
+        L = (32, 64, 128)[i % 3]
+        r["L"] = L
+        cap = gz.bound(n, code, L)
+        o = torch.empty(cap, dtype=torch.uint8, device="cuda")
+        nb = torch.zeros(1, dtype=torch.int64, device="cuda")
+        ins.append(x)
+        outs.append(o)
+        nbs.append(nb)
+        items.append({"in": x, "out": o, "out_bytes": nb, "n": n, "out_cap": cap,
+                      "eb": r["eb"], "dtype": code, "block_len": L})
+    say("requests ready, bytes", sum(x.numel() * x.element_size() for x in ins))
+    ctx.batch(gz.GZ_OP_COMPRESS, ctx.requests(items))
+    torch.cuda.synchronize()
+    say("compressed, status", ctx.device_status())
+    ys, ditems = [], []
+    for x, o, nb, r in zip(ins, outs, nbs, reqs):
+        y = torch.empty_like(x)
+        ys.append(y)
+        ditems.append({"in": o, "out": y, "n": r["n"], "in_bytes": int(nb.item()),
+                       "dtype": gz.GZ_F32 if x.dtype == torch.float32 else gz.GZ_F64,
+                       "block_len": r["L"]})
+    ctx.batch(gz.GZ_OP_DECOMPRESS, ctx.requests(ditems))
+    torch.cuda.synchronize()
+    say("decompressed, status", ctx.device_status())
+    for x, y, r in zip(ins, ys, reqs):
+        assert float((y.double() - x.double()).abs().max()) <= r["eb"]
+    for i in range(0, len(reqs), 128):
+        xh = ins[i].cpu().numpy()
+        want = oracle.compress(xh, reqs[i]["eb"], block_len=reqs[i]["L"])
+        got = outs[i][:int(nbs[i].item())].cpu().numpy()
+        assert got.tobytes() == want.tobytes(), i
+        assert ys[i].cpu().numpy().tobytes() == oracle.decompress(want).tobytes(), i
+    assert ctx.device_status() == 0
+    ctx.close()
