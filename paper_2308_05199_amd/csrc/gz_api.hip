@@ -25,6 +25,7 @@
 using gzk::Ctl;
 using gzk::Ctrl;
 using gzk::Job;
+using gzk::job_ptr;
 
 namespace {
 
@@ -282,10 +283,10 @@ gz_status build_requests(gz_ctx* c, gz_op op, const gz_request* r, uint32_t nreq
     if (q.n && (!q.in || !q.out)) return GZ_EINVAL;
     if (q.n * (uint64_t)esize(q.dtype) >= (1ull << 34)) return GZ_EINVAL;
     J.dtype = q.dtype;
-    J.in = q.in;
-    J.out = q.out;
-    J.local = q.local;
-    J.out_bytes = (unsigned long long*)q.d_out_bytes;
+    J.in = job_ptr(q.in);
+    J.out = job_ptr(q.out);
+    J.local = job_ptr(q.local);
+    J.out_bytes = job_ptr((unsigned long long*)q.d_out_bytes);
     J.in_bytes = q.in_bytes;
     J.job = j;
     set_geom(J, q.n, L, tpb);
@@ -458,9 +459,9 @@ gz_status gz_compress(gz_ctx* c, const void* d_in, uint64_t n, gz_dtype dtype, d
   if (!tpb_fits(c, dtype == GZ_F64, tile_mode(p), tpb)) return GZ_EUNSUPPORTED;
   set_geom(J, n, L, tpb);
   if (J.nstrips > c->max_strips) return GZ_ENOSPC;
-  J.in = d_in;
-  J.out = d_out;
-  J.out_bytes = (unsigned long long*)d_out_bytes;
+  J.in = job_ptr(d_in);
+  J.out = job_ptr(d_out);
+  J.out_bytes = job_ptr((unsigned long long*)d_out_bytes);
   if (tile_mode(p)) {
     if (dtype != GZ_F32) return GZ_EUNSUPPORTED;
     if (n % (8ull * p->nx) != 0) return GZ_EINVAL;
@@ -489,9 +490,9 @@ gz_status gz_decompress(gz_ctx* c, const void* d_in, uint64_t in_bytes, uint64_t
   if (!tpb_fits(c, dtype == GZ_F64, tile_mode(p), tpb)) return GZ_EUNSUPPORTED;
   set_geom(J, n, L, tpb);
   if (J.nstrips > c->max_strips) return GZ_ENOSPC;
-  J.in = d_in;
+  J.in = job_ptr(d_in);
   J.in_bytes = in_bytes;
-  J.out = d_out;
+  J.out = job_ptr(d_out);
   if (tile_mode(p)) {
     if (dtype != GZ_F32) return GZ_EUNSUPPORTED;
     if (n % (8ull * p->nx) != 0) return GZ_EINVAL;
@@ -524,11 +525,11 @@ gz_status gz_fused_reduce_step(gz_ctx* c, const void* d_cmp_in, uint64_t in_byte
   if (!tpb_fits(c, false, false, tpb)) return GZ_EUNSUPPORTED;
   set_geom(J, n, L, tpb);
   if (J.nstrips > c->max_strips) return GZ_ENOSPC;
-  J.in = d_cmp_in;
+  J.in = job_ptr(d_cmp_in);
   J.in_bytes = in_bytes;
-  J.local = d_local;
-  J.out = d_cmp_out;
-  J.out_bytes = (unsigned long long*)d_out_bytes;
+  J.local = job_ptr(d_local);
+  J.out = job_ptr(d_cmp_out);
+  J.out_bytes = job_ptr((unsigned long long*)d_out_bytes);
   const uint32_t grid = pick_grid(c, 2, GZ_F32, L, tpb, J.nstrips, p);
   return hip_status(gzk::launch_single(2, J, c->ctl(), tpb, grid, (hipStream_t)stream));
 }
@@ -547,9 +548,9 @@ gz_status gz_decompress_add(gz_ctx* c, const void* d_in, uint64_t in_bytes, uint
   if (!tpb_fits(c, false, false, tpb)) return GZ_EUNSUPPORTED;
   set_geom(J, n, L, tpb);
   if (J.nstrips > c->max_strips) return GZ_ENOSPC;
-  J.in = d_in;
+  J.in = job_ptr(d_in);
   J.in_bytes = in_bytes;
-  J.out = d_acc;
+  J.out = job_ptr(d_acc);
   const uint32_t grid = pick_grid(c, 3, GZ_F32, L, tpb, J.nstrips, p);
   return hip_status(gzk::launch_single(3, J, c->ctl(), tpb, grid, (hipStream_t)stream));
 }
@@ -578,10 +579,10 @@ gz_status gz_scatter_compress(gz_ctx* c, const void* d_root, gz_dtype dtype,
     if (n * (uint64_t)esize(dtype) >= (1ull << 34)) return GZ_EINVAL;
     span = std::max(span, h_displs[j] + n);
     set_geom(J, n, L, tpb);
-    J.in = (const uint8_t*)d_root + h_displs[j] * esize(dtype);
-    J.out = d_out;
-    J.out_bytes = (unsigned long long*)(d_chunk_bytes + j);
-    J.chunk_off = (unsigned long long*)(d_chunk_offsets + j);
+    J.in = job_ptr((const uint8_t*)d_root + h_displs[j] * esize(dtype));
+    J.out = job_ptr(d_out);
+    J.out_bytes = job_ptr((unsigned long long*)(d_chunk_bytes + j));
+    J.chunk_off = job_ptr((unsigned long long*)(d_chunk_offsets + j));
     J.fixed_off = fixed;
     J.strip0 = strip;
     J.chain0 = 0;
@@ -628,10 +629,10 @@ gz_status gz_scatter_decompress(gz_ctx* c, const void* d_packed, uint64_t packed
     if (n * (uint64_t)esize(dtype) >= (1ull << 34)) return GZ_EINVAL;
     span = std::max(span, h_displs[j] + n);
     set_geom(J, n, L, tpb);
-    J.in = d_packed;
-    J.in_off = (const unsigned long long*)d_chunk_offsets;
+    J.in = job_ptr(d_packed);
+    J.in_off = job_ptr((const unsigned long long*)d_chunk_offsets);
     J.in_bytes = packed_bytes;
-    J.out = (uint8_t*)d_root + h_displs[j] * esize(dtype);
+    J.out = job_ptr((uint8_t*)d_root + h_displs[j] * esize(dtype));
     J.strip0 = J.chain0 = strip;
     J.job = j;
     strip += J.nstrips;
@@ -938,7 +939,7 @@ gz_status gz_tile_trial(gz_ctx* c, const float* d_in, uint64_t n, uint32_t nx, d
   J.dtype = GZ_F32;
   if (!set_bound(J, GZ_F32, eb)) return GZ_EINVAL;
   if (!n) return GZ_OK;
-  J.in = d_in;
+  J.in = job_ptr(d_in);
   J.n = n;
   J.B = n / 64;
   J.nx = nx;

@@ -26,15 +26,31 @@ struct Ctrl {
   uint32_t pad[60];
 };
 
+// Device code sees the job's buffers as global-address-space pointers: a
+// generic pointer read from memory (a batch's job table) would make every
+// access through it a flat instruction, which waits on the LDS counter too
+// and is ordered against LDS accesses.  The layout is the same on the host.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define GZ_GLOBAL __attribute__((address_space(1)))
+#else
+#define GZ_GLOBAL
+#endif
+
+// Host code stores plain device pointers into a Job through this cast.
+template <typename T>
+inline GZ_GLOBAL T* job_ptr(T* p) {
+  return (GZ_GLOBAL T*)p;
+}
+
 // One independent stream to encode, decode or fuse.  Geometry fields
 // describe the stream written (encode/fused) or expected (decode).
 struct Job {
-  const void* in;                   // T[n] | stream
-  const float* local;               // fused addend
-  void* out;                        // stream | T[n]
-  unsigned long long* out_bytes;    // encode: size of the stream written
-  unsigned long long* chunk_off;    // scatter: offset of this stream
-  const unsigned long long* in_off; // scatter decode: offset of this stream in `in`
+  GZ_GLOBAL const void* in;                   // T[n] | stream
+  GZ_GLOBAL const float* local;               // fused addend
+  GZ_GLOBAL void* out;                        // stream | T[n]
+  GZ_GLOBAL unsigned long long* out_bytes;    // encode: size of the stream written
+  GZ_GLOBAL unsigned long long* chunk_off;    // scatter: offset of this stream
+  GZ_GLOBAL const unsigned long long* in_off; // scatter decode: offset of this stream in `in`
   uint64_t n;
   uint64_t in_bytes;                // decode/fused: bytes readable at `in`
   uint64_t strip0;                  // first global strip of this job

@@ -1212,33 +1212,46 @@ __device__ __forceinline__ double step_of<double>(const Smem& sm) { return sm.t6
 // where lo <= src is readable stream memory.
 __device__ __forceinline__ const uint32_t* copy_in(const uint32_t* src, uint32_t P) {
   const uint32_t tid = threadIdx.x, TPB = blockDim.x;
-  const uintptr_t a = (uintptr_t)src;
-  const uint32_t delta = (uint32_t)((a & 15u) >> 2);
-  const u4u* al = (const u4u*)(a - 4 * delta);
+  // realigned by pointer arithmetic (an integer round trip would lose the
+  // pointer's global address space)
+  const uint32_t delta = (uint32_t)(((uintptr_t)src & 15u) >> 2);
+  const u4u* al = (const u4u*)(src - delta);
   const uint32_t nch = (delta + P + 3) / 4;  // 16-byte chunks touched
   const uint32_t full = (delta + P) / 4;     // chunks entirely inside
   u4u* dstc = (u4u*)g_stage;
-  for (uint32_t k0 = 0; k0 < nch; k0 += 4 * TPB) {
+  // whole chunks, four independent loads in flight per lane.  The first
+  // 8 TPB chunks (all of an fp32 strip: a payload never exceeds the raw
+  // size) are straight-line code: in a loop, the next pass's loads into the
+  // same registers make the compiler wait for every outstanding memory
+  // operation before each load.  fp64 strips may need the loop after it.
+  // Lanes past the end re-read the last whole chunk instead of branching
+  // around the load (a conditional load leaves a merge of registers that the
+  // compiler resolves with copies, which wait for the load at once).
+#pragma unroll
+  for (uint32_t h = 0; h < 2; ++h) {
+    const uint32_t k0 = h * 4 * TPB;
+    if (full <= k0) break;
     u4u r[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const uint32_t k = k0 + u * TPB + tid;
-      if (k < full) {
-        r[u] = al[k];
-      } else if (k < nch) {
-        const uint32_t* p = (const uint32_t*)(al + k);
-        const uint32_t lim = delta + P - 4 * k;  // valid dwords in this chunk
-        r[u].x = lim > 0 ? p[0] : 0u;
-        r[u].y = lim > 1 ? p[1] : 0u;
-        r[u].z = lim > 2 ? p[2] : 0u;
-        r[u].w = 0u;
-      }
-    }
+    for (int u = 0; u < 4; ++u) r[u] = al[min(k0 + u * TPB + tid, full - 1)];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const uint32_t k = k0 + u * TPB + tid;
-      if (k < nch) dstc[k] = r[u];
+      if (k < full) dstc[k] = r[u];
     }
+  }
+  for (uint32_t k = 8 * TPB + tid; k < full; k += TPB) dstc[k] = al[k];
+  // the range ends inside the last chunk: dword loads, so that nothing past
+  // it is read
+  if (full < nch && tid == 0) {
+    const uint32_t* p = (const uint32_t*)(al + full);
+    const uint32_t lim = delta + P - 4 * full;  // 1..3 valid dwords
+    u4u r;
+    r.x = p[0];
+    r.y = lim > 1 ? p[1] : 0u;
+    r.z = lim > 2 ? p[2] : 0u;
+    r.w = 0u;
+    dstc[full] = r;
   }
   return g_stage + delta;
 }
@@ -1368,12 +1381,14 @@ __device__ bool decode_strip(const Job& J, const uint8_t* in, uint64_t in_bytes,
   }
   const bool rng = ok && E <= En && En <= pay_dw && En - E <= (uint64_t)TPB * SEG * EW;
   const uint32_t P = rng ? (uint32_t)(En - E) : 0u;
+  // the header byte is loaded before the payload copy, in the same round
+  // trip (after it, it would cost a second one)
+  const uint32_t hb = (rng && exists) ? (uint32_t)in[J.hdr_off + b] : 0u;
   const uint32_t* S = g_stage + 4;
   if (rng) S = copy_in((const uint32_t*)(in + J.pay_off) + E, P);
 
   const uint32_t m = FULL ? (uint32_t)L
                           : (exists ? (uint32_t)min((uint64_t)L, J.n - b * (uint64_t)L) : 0u);
-  const uint32_t hb = (rng && exists) ? (uint32_t)in[J.hdr_off + b] : 0u;
   const uint32_t kind = hb >> 5, F = hb & 31u;
   uint32_t size_dw = 0;
   bool hv = true;
