@@ -1547,13 +1547,16 @@ __device__ __forceinline__ void decompress_tp_body(const Job& J, uint64_t s, con
     __syncthreads();  // every lane has read its payload words
     lane_to_lds<T>(v);
     __syncthreads();
-    const uint64_t s0 = s * blockDim.x * (uint64_t)SEG;
-    lds_to_strip<T>((T*)J.out + s0, FULL ? (uint64_t)blockDim.x * SEG : J.n - s0);
-    if (threadIdx.x == 0) {  // read by the next strip after the loop's barrier
+    // read by the next strip after the loop's barrier; written before the
+    // stores are issued, so that waiting for the table words does not also
+    // wait for this strip's stores (the wait counter is in order)
+    if (threadIdx.x == 0) {
       sm.tp_t0 = p0;
       sm.tp_t1 = p1;
       sm.tp_key = nxt + 1u;
     }
+    const uint64_t s0 = s * blockDim.x * (uint64_t)SEG;
+    lds_to_strip<T>((T*)J.out + s0, FULL ? (uint64_t)blockDim.x * SEG : J.n - s0);
   }
 }
 
