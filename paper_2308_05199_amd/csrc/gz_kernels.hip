@@ -306,18 +306,22 @@ __device__ uint64_t lookback(const Ctl& C, uint64_t gs, uint64_t chain0, uint32_
   for (;;) {
     uint32_t flag[LB_SUB];
     uint64_t val[LB_SUB];
+    // every load is issued before any is used: lanes before the chain's
+    // start read its first word (a load under a divergent branch is merged
+    // by register copies that wait for it at once, one round trip per load)
+    uint64_t w[LB_SUB];
 #pragma unroll
     for (int m = 0; m < LB_SUB; ++m) {
       const int64_t idx = top - 64 * m - lane;
-      if (idx >= (int64_t)chain0) {
-        const uint64_t w = ld_agent(C.status + idx);
-        const bool cur = (uint32_t)((w >> 34) & 0x0FFFFFFFu) == (ep & 0x0FFFFFFFu);
-        flag[m] = cur ? (uint32_t)(w >> 62) : 0u;
-        val[m] = w & VMASK;
-      } else {
-        flag[m] = 2;
-        val[m] = 0;
-      }
+      w[m] = ld_agent(C.status + (idx >= (int64_t)chain0 ? idx : (int64_t)chain0));
+    }
+#pragma unroll
+    for (int m = 0; m < LB_SUB; ++m) {
+      const int64_t idx = top - 64 * m - lane;
+      const bool cur = (uint32_t)((w[m] >> 34) & 0x0FFFFFFFu) == (ep & 0x0FFFFFFFu);
+      const bool in_chain = idx >= (int64_t)chain0;
+      flag[m] = in_chain ? (cur ? (uint32_t)(w[m] >> 62) : 0u) : 2u;
+      val[m] = in_chain ? (w[m] & VMASK) : 0ull;
     }
     uint64_t part = 0;  // this lane's share of the resolved sub-windows
     int resolved = 0;   // sub-windows fully added in
@@ -1334,9 +1338,16 @@ __device__ __forceinline__ void table_words(const Job& J, const uint8_t* in, uin
   const uint32_t* table = (const uint32_t*)(in + HDR);
   const uint64_t sb0 = s * (uint64_t)(blockDim.x * SEG / SUPER);
   const uint64_t sbn = sb0 + blockDim.x * SEG / SUPER;
-  const bool tab_ok = in_bytes >= J.pay_off;
-  T0 = (tab_ok && sb0 < J.NS) ? table[sb0] : 0u;
-  T1 = (tab_ok && sbn < J.NS) ? table[sbn] : 0u;
+  T0 = 0;
+  T1 = 0;
+  if (in_bytes >= J.pay_off && J.NS) {
+    // both loads issued before either is used (clamped indices, not
+    // conditional loads, which the compiler waits for one at a time)
+    const uint32_t a = table[min(sb0, J.NS - 1)];
+    const uint32_t b = table[min(sbn, J.NS - 1)];
+    T0 = sb0 < J.NS ? a : 0u;
+    T1 = sbn < J.NS ? b : 0u;
+  }
 }
 
 // pkey (nonzero): the strip's table words may already sit in sm.tp_t0/t1,
@@ -1370,7 +1381,11 @@ __device__ bool decode_strip(const Job& J, const uint8_t* in, uint64_t in_bytes,
   // is read now, with the others, not after the scan
   const bool exists = FULL || b < J.B;
   const bool sb_lane = exists && (seg & (SUPER / SEG - 1)) == 0;
-  const uint32_t Tsb = (sb_lane && in_bytes >= J.pay_off) ? table[seg / (SUPER / SEG)] : 0u;
+  uint32_t Tsb = 0;
+  if (in_bytes >= J.pay_off && J.NS) {  // every lane loads (clamped): no wait per load
+    const uint32_t x = table[min(seg / (SUPER / SEG), J.NS - 1)];
+    Tsb = sb_lane ? x : 0u;
+  }
   if (sm.hdr_job != J.job + 1) check_header(J, in, in_bytes, sm);
   const bool ok = sm.hdr_ok != 0;  // implies in_bytes >= J.pay_off
   const uint64_t pay_dw = sm.paydw;
