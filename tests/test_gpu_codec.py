@@ -408,3 +408,41 @@ def test_quantize_sampled_bit_patterns(ctx, oracle):
         wq, wf = oracle.quantize(x, eb)
         assert np.array_equal(f.cpu().numpy().astype(bool), wf)
         assert np.array_equal(q.cpu().numpy(), wq)
+
+
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+@pytest.mark.parametrize("kind", ["dense", "raw"])
+def test_decompress_dense_payloads(ctx, oracle, dt, kind):
+    """Strips whose payload is most of (dense: ~24-bit residuals) or all of
+    (raw: every block stored raw, |x / 2eb| >= 2^29) the raw size, plus a
+    ragged last strip: the payload copy then needs more than one batch of
+    16-byte loads per lane, fp64 strips the copy loop past the first eight
+    batches, and the range ends inside a 16-byte chunk."""
+    import torch
+    say("decompress dense payloads", dt.__name__, kind)
+    g = np.random.default_rng(31)
+    n = 3 * 32768 + 333
+    if kind == "dense":
+        x = g.uniform(-1.0, 1.0, n).astype(dt)
+    else:
+        x = g.uniform(1e3, 2e3, n).astype(dt) * np.where(g.random(n) < 0.5, -1, 1).astype(dt)
+    # dense: about 20 (fp32) or 27 (fp64) bits per residual, coded L1D
+    eb = {"dense": 1e-6 if dt == np.float32 else 1e-8, "raw": 1e-7}[kind]
+    s = oracle.compress(x, eb)
+    want = oracle.decompress(s)
+    least = {"dense": 0.6 if dt == np.float32 else 0.4, "raw": 0.99}[kind]
+    assert s.size > least * x.nbytes
+    tdt = torch.float32 if dt == np.float32 else torch.float64
+    for tpb in (128, 256, 512, 1024):
+        say("  threads", tpb)
+        y = unless_unsupported(lambda: ctx.decompress(dev(s), n, dtype=tdt, threads=tpb), dt, tpb)
+        if y is None:
+            continue
+        torch.cuda.synchronize()
+        assert y.cpu().numpy().view(np.uint8).tobytes() == want.view(np.uint8).tobytes()
+        if dt == np.float32:
+            acc = dev(np.ones(n, np.float32))
+            ctx.decompress_add(dev(s), acc, threads=tpb)
+            torch.cuda.synchronize()
+            assert acc.cpu().numpy().tobytes() == (want + np.float32(1)).tobytes()
+    assert_ok(ctx)
