@@ -545,6 +545,31 @@ __device__ __forceinline__ void strip_to_lds(const T* __restrict__ src, uint64_t
   }
 }
 
+// A whole input strip into the padded LDS layout with eight unconditional
+// 16-byte loads in flight per lane, in straight-line code (the general copy
+// above waits for every outstanding memory operation, the previous strip's
+// stores included, at the top of each pass, and after each load of a
+// branch that has a partial-chunk side).  Used by the fp32 encoder, whose
+// registers are free at this point.
+template <typename T>
+__device__ __forceinline__ void strip_to_lds_whole(const T* __restrict__ src) {
+  constexpr uint32_t SEGW = 32 * (sizeof(T) / 4), STR = seg_stride<T>();
+  const uint32_t tid = threadIdx.x, TPB = blockDim.x;
+  const uint32_t* s32 = (const uint32_t*)src;
+  uint32_t* buf = g_stage + 4;
+#pragma unroll
+  for (uint32_t h = 0; h < SEGW / 4; h += 8) {
+    u4u r[8];
+#pragma unroll
+    for (uint32_t u = 0; u < 8; ++u) r[u] = *(const u4u*)(s32 + 4 * ((h + u) * TPB + tid));
+#pragma unroll
+    for (uint32_t u = 0; u < 8; ++u) {
+      const uint32_t dw = 4 * ((h + u) * TPB + tid);
+      *(u4u*)(buf + (dw / SEGW) * STR + dw % SEGW) = r[u];
+    }
+  }
+}
+
 // The lane index as a value the compiler cannot see through: addresses
 // derived from it are formed where they are used, not hoisted out of the
 // persistent loop into registers held across a whole strip.
@@ -1448,7 +1473,8 @@ __device__ __forceinline__ void compress_body(const Job& J, uint64_t s, uint64_t
   const uint64_t e0 = seg * SEG;
   const uint32_t vcnt = FULL ? 32u : (e0 >= J.n ? 0u : (uint32_t)min((uint64_t)SEG, J.n - e0));
   const uint64_t s0 = s * blockDim.x * (uint64_t)SEG;
-  strip_to_lds<T>((const T*)J.in + s0, FULL ? (uint64_t)blockDim.x * SEG : J.n - s0);
+  if (FULL && sizeof(T) == 4) strip_to_lds_whole<T>((const T*)J.in + s0);
+  else strip_to_lds<T>((const T*)J.in + s0, FULL ? (uint64_t)blockDim.x * SEG : J.n - s0);
   __syncthreads();
   T v[32];
   lane_from_lds<T>(v);
