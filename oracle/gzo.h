@@ -67,7 +67,11 @@
  * Selector (mode 1, select = 0): 16 int8 features of the tile's q, an int8
  * MLP 16->32->3 with int32 accumulation, a rounding arithmetic shift and a
  * [0,127] clamp between the layers, argmax with the lowest index winning
- * ties; output 0 NONE, 1 L1D, 2 L2D.  select = 1 is the exhaustive trial:
+ * ties; output 0 NONE, 1 L1D, 2 L2D.  The features are bit lengths:
+ *   f0..f3   |q(r,c)|                                at (0,0) (2,5) (5,2) (7,7)
+ *   f4..f7   |q(r,c) - q(r,c-1)|                     at (1,1) (3,6) (4,3) (6,7)
+ *   f8..f11  |q(r,c) - q(r-1,c)|                     at (1,3) (3,1) (5,6) (7,4)
+ *   f12..f15 |q(r,c) - q(r,c-1) - q(r-1,c) + q(r-1,c-1)| at (1,5) (2,2) (5,5) (6,1)  select = 1 is the exhaustive trial:
  * smallest size among NONE, L1D, L2D, ties to the first in that order.
  * select = 2 always uses L1D.
  */

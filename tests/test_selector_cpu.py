@@ -96,3 +96,91 @@ def test_mode1_select0_uses_the_network(oracle):
     assert set(int(h) >> 5 for h in hdr) <= {0, 2, 7}
     y = oracle.decompress(s)
     assert np.all(np.abs(y.astype(np.float64) - x) <= 1e-3)
+
+
+# ---- the 16 tile features.  Their definition (gzo.h): bit lengths of
+# |q| at (0,0) (2,5) (5,2) (7,7); of the row differences q(r,c) - q(r,c-1)
+# at (1,1) (3,6) (4,3) (6,7); of the column differences q(r,c) - q(r-1,c) at
+# (1,3) (3,1) (5,6) (7,4); of the second-order residuals q(r,c) - q(r,c-1)
+# - q(r-1,c) + q(r-1,c-1) at (1,5) (2,2) (5,5) (6,1).
+MAG = [(0, 0), (2, 5), (5, 2), (7, 7)]
+ROW = [(1, 1), (3, 6), (4, 3), (6, 7)]
+COL = [(1, 3), (3, 1), (5, 6), (7, 4)]
+DIAG = [(1, 5), (2, 2), (5, 5), (6, 1)]
+
+
+def _bitlen(v):
+    v = abs(int(v))
+    return v.bit_length()
+
+
+def _features_numpy(q):
+    t = np.asarray(q, np.int64).reshape(8, 8)
+    f = [_bitlen(t[r, c]) for r, c in MAG]
+    f += [_bitlen(t[r, c] - t[r, c - 1]) for r, c in ROW]
+    f += [_bitlen(t[r, c] - t[r - 1, c]) for r, c in COL]
+    f += [_bitlen(t[r, c] - t[r, c - 1] - t[r - 1, c] + t[r - 1, c - 1]) for r, c in DIAG]
+    return np.array(f, np.int8)
+
+
+def test_tile_features_restated(oracle):
+    """Random tiles over the whole quantised range (|q| <= 2^29 - 1, where
+    second-order residuals need 31 bits) and small ones: the oracle's
+    features equal a separate statement of the definition."""
+    g = np.random.default_rng(11)
+    lim = 2 ** 29 - 1
+    tiles = [g.integers(-lim, lim + 1, 64) for _ in range(300)]
+    tiles += [g.integers(-40, 41, 64) for _ in range(300)]
+    r, c = np.mgrid[0:8, 0:8]
+    tiles.append(np.where((r + c) % 2 == 0, lim, -lim).reshape(64))
+    tiles.append(np.full(64, -lim))
+    for q in tiles:
+        assert np.array_equal(oracle.tile_features(q), _features_numpy(q))
+    f = oracle.tile_features(tiles[-2])
+    assert list(f) == [29] * 4 + [30] * 8 + [31] * 4
+
+
+@pytest.mark.parametrize("a,b", [(0, 1), (7, 3), (-100, 25), (1 << 20, -(1 << 12))])
+def test_tile_features_on_ramps(oracle, a, b):
+    """Closed forms that tell the feature groups apart: a row ramp
+    q = a + b*c has row differences b and no column or second-order ones;
+    a column ramp the reverse; the bilinear tile q = b*r*c has row
+    differences b*r, column differences b*c and second-order residuals b."""
+    r, c = np.mgrid[0:8, 0:8]
+    bl = _bitlen(b)
+    f = oracle.tile_features((a + b * c).reshape(64))
+    assert list(f[4:8]) == [bl] * 4 and list(f[8:16]) == [0] * 8
+    assert list(f[0:4]) == [_bitlen(a + b * cc) for _, cc in MAG]
+    f = oracle.tile_features((a + b * r).reshape(64))
+    assert list(f[4:8]) == [0] * 4 and list(f[8:12]) == [bl] * 4 and list(f[12:16]) == [0] * 4
+    assert list(f[0:4]) == [_bitlen(a + b * rr) for rr, _ in MAG]
+    f = oracle.tile_features((b * r * c).reshape(64))
+    assert list(f[4:8]) == [_bitlen(b * rr) for rr, _ in ROW]
+    assert list(f[8:12]) == [_bitlen(b * cc) for _, cc in COL]
+    assert list(f[12:16]) == [bl] * 4
+
+
+def test_tile_features_read_only_their_positions(oracle):
+    """Brute force over the 64 positions: a large change of q(r,c) alters
+    exactly the features whose definition reads (r,c)."""
+    base = np.zeros(64, np.int64)
+    f0 = oracle.tile_features(base)
+    for i in range(64):
+        rr, cc = divmod(i, 8)
+        reads = set()
+        for k, (r, c) in enumerate(MAG):
+            if (r, c) == (rr, cc):
+                reads.add(k)
+        for k, (r, c) in enumerate(ROW):
+            if (rr, cc) in ((r, c), (r, c - 1)):
+                reads.add(4 + k)
+        for k, (r, c) in enumerate(COL):
+            if (rr, cc) in ((r, c), (r - 1, c)):
+                reads.add(8 + k)
+        for k, (r, c) in enumerate(DIAG):
+            if (rr, cc) in ((r, c), (r, c - 1), (r - 1, c), (r - 1, c - 1)):
+                reads.add(12 + k)
+        q = base.copy()
+        q[i] = 1 << 20
+        changed = set(np.nonzero(oracle.tile_features(q) != f0)[0].tolist())
+        assert changed == reads, (rr, cc)
