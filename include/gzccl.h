@@ -256,6 +256,27 @@ gz_status gz_mlp_grad(gz_ctx* ctx, const float* d_w, const int8_t* d_feat,
 gz_status gz_mlp_adam(gz_ctx* ctx, float* d_w, const float* d_grad, float* d_m,
                       float* d_v, uint32_t step, float lr, gz_stream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): gz_compress
+ * without a context.  Arguments, bytes and host-side errors are those of
+ * gz_compress, except that the MLP selector (mode 1, select 0) is not
+ * available (GZ_EINVAL).  The workspace is a device-resident array of
+ * 263,424 bytes that the library holds on each device until the process
+ * ends; it serves streams of at most 32768 strips (2^30 fp32 elements at the
+ * default 1024 threads, 2^28 fp64 elements at 256), larger inputs return
+ * GZ_ENOSPC with nothing enqueued.  The call allocates nothing: its first
+ * call on a device only looks up the array's address.  It enqueues the
+ * compression and a one-wave kernel that writes the device status of the
+ * call (GZ_OK, or GZ_ETIMEOUT when a look-back wait expired and the stream
+ * is invalid) to *d_status (a caller-owned device word; may be NULL) and
+ * clears it.  Every call on one device shares that device's array: calls
+ * that overlap in time on one device (several streams or threads) race and
+ * must be serialised by the caller. */
+gz_status gz_compress_noalloc(const void* d_in, uint64_t n, gz_dtype dtype, double eb,
+                              const gz_params* p, void* d_out, uint64_t out_cap,
+                              uint64_t* d_out_bytes, uint32_t* d_status,
+                              gz_stream_t stream);
+
 const char* gz_status_str(gz_status s);
 
 #ifdef __cplusplus

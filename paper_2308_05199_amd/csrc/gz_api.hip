@@ -14,6 +14,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -441,9 +442,16 @@ gz_status gz_quantize(gz_ctx* c, const void* d_in, uint64_t n, gz_dtype dtype, d
   return hip_status(gzk::launch_quantize(d_in, n, J, d_q, d_fail, (hipStream_t)stream));
 }
 
-gz_status gz_compress(gz_ctx* c, const void* d_in, uint64_t n, gz_dtype dtype, double eb,
-                      const gz_params* p, void* d_out, uint64_t out_cap, uint64_t* d_out_bytes,
-                      gz_stream_t stream) {
+}  // extern "C"
+
+namespace {
+
+// Validates a compression and enqueues its one launch on the context's
+// workspace (a real context, or the device-resident one of
+// gz_compress_noalloc).
+gz_status compress_impl(gz_ctx* c, const void* d_in, uint64_t n, gz_dtype dtype, double eb,
+                        const gz_params* p, void* d_out, uint64_t out_cap,
+                        uint64_t* d_out_bytes, gz_stream_t stream) {
   uint32_t L;
   if (!c || !d_out || (dtype != GZ_F32 && dtype != GZ_F64) || !params_ok(p, L))
     return GZ_EINVAL;
@@ -474,6 +482,16 @@ gz_status gz_compress(gz_ctx* c, const void* d_in, uint64_t n, gz_dtype dtype, d
   }
   const uint32_t grid = pick_grid(c, 0, dtype, L, tpb, J.nstrips, p);
   return hip_status(gzk::launch_single(0, J, c->ctl(), tpb, grid, (hipStream_t)stream));
+}
+
+}  // namespace
+
+extern "C" {
+
+gz_status gz_compress(gz_ctx* c, const void* d_in, uint64_t n, gz_dtype dtype, double eb,
+                      const gz_params* p, void* d_out, uint64_t out_cap, uint64_t* d_out_bytes,
+                      gz_stream_t stream) {
+  return compress_impl(c, d_in, n, dtype, eb, p, d_out, out_cap, d_out_bytes, stream);
 }
 
 gz_status gz_decompress(gz_ctx* c, const void* d_in, uint64_t in_bytes, uint64_t n,
@@ -962,6 +980,89 @@ gz_status gz_mlp_adam(gz_ctx* c, float* d_w, const float* d_grad, float* d_m, fl
   const float bc2 = (float)(1.0 - pow(0.999, (double)step));
   return hip_status(gzs::launch_mlp_adam(d_w, d_grad, d_m, d_v, lr, bc1, bc2,
                                          (hipStream_t)stream));
+}
+
+}  // extern "C"
+
+// ---- compression without allocation, for callers that cannot allocate
+// device memory (code under HIP graph capture, serving loops).  Its
+// workspace is the file-scope device array `scratch`: the control block,
+// 1 KiB of selector weights (zero: the MLP selector is not available here)
+// and one look-back word per strip.  Each device holds its own copy until
+// the process ends.  The last workgroup of every launch leaves the ticket
+// counters at zero and the look-back words are tagged with a launch epoch,
+// so nothing needs clearing between calls; the finishing kernel reports and
+// clears the sticky error word.  Calls that overlap on one device race on
+// the array.
+namespace {
+
+constexpr uint64_t NA_MAX_STRIPS = 32768;
+constexpr size_t NA_CTRL = 0, NA_BLOB = sizeof(Ctrl), NA_STATUS = NA_BLOB + 1024;
+constexpr size_t NA_BYTES = NA_STATUS + NA_MAX_STRIPS * 8;
+constexpr int NA_MAX_DEV = 64;
+
+struct NoAllocDev {
+  std::once_flag once;
+  gz_status setup = GZ_EHIP;
+  gz_ctx ctx;  // host description of the device-resident workspace
+};
+NoAllocDev g_noalloc[NA_MAX_DEV];
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[NA_BYTES];
+
+namespace {
+
+// Once per device, with that device current: the array's device address
+// (host code never uses the symbol itself as an address) and the launch
+// limits of the device.
+gz_status noalloc_setup(int device, gz_ctx& c) {
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return GZ_EHIP;
+  c.device = device;
+  if (hipDeviceGetAttribute(&c.cus, hipDeviceAttributeMultiprocessorCount, device) !=
+      hipSuccess)
+    return GZ_EHIP;
+  int wclk_khz = 0;
+  if (hipDeviceGetAttribute(&wclk_khz, hipDeviceAttributeWallClockRate, device) != hipSuccess ||
+      wclk_khz <= 0)
+    wclk_khz = 100000;
+  c.wait_ticks = (uint64_t)wclk_khz * 1000ull;
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) !=
+          hipSuccess ||
+      lds <= 0)
+    lds = 65536;
+  c.lds_max = (size_t)lds;
+  uint8_t* base = (uint8_t*)ptr;
+  c.ctrl = (Ctrl*)(base + NA_CTRL);
+  c.blob = base + NA_BLOB;
+  c.blob_loaded = false;
+  c.status = (unsigned long long*)(base + NA_STATUS);
+  c.jobbase = nullptr;  // single streams only (no packed chains)
+  c.max_strips = NA_MAX_STRIPS;
+  c.max_elems = 0;
+  c.max_jobs = 0;
+  return GZ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gz_status gz_compress_noalloc(const void* d_in, uint64_t n, gz_dtype dtype, double eb,
+                              const gz_params* p, void* d_out, uint64_t out_cap,
+                              uint64_t* d_out_bytes, uint32_t* d_status, gz_stream_t stream) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return GZ_EHIP;
+  if (dev < 0 || dev >= NA_MAX_DEV) return GZ_EUNSUPPORTED;
+  NoAllocDev& d = g_noalloc[dev];
+  std::call_once(d.once, [&] { d.setup = noalloc_setup(dev, d.ctx); });
+  if (d.setup != GZ_OK) return d.setup;
+  gz_status r = compress_impl(&d.ctx, d_in, n, dtype, eb, p, d_out, out_cap, d_out_bytes, stream);
+  if (r != GZ_OK) return r;
+  return hip_status(gzk::launch_finish(d.ctx.ctl(), d_status, (hipStream_t)stream));
 }
 
 }  // extern "C"

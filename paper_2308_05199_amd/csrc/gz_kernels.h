@@ -27,6 +27,9 @@ hipError_t launch_tile_trial(const Job& J, int8_t* feat, uint32_t* sizes, uint8_
                              hipStream_t st);
 hipError_t launch_fill(void* x, uint64_t n, uint32_t dtype, hipStream_t st);  // tuning input
 hipError_t launch_reset(const Ctl& C, hipStream_t st);
+// writes the sticky device status (a gz_status code) to *status, if given,
+// and clears it
+hipError_t launch_finish(const Ctl& C, uint32_t* status, hipStream_t st);
 // Kernels of occupancy_blocks: ops 0-2 as launch_single, OCC_BATCH + k = batched
 // op k (dtype 1: a batch with fp64), tile compress/decompress, single-stream
 // decode-and-accumulate.

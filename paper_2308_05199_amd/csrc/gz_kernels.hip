@@ -1932,6 +1932,17 @@ __global__ void k_reset(Ctl C) {
   }
 }
 
+// Reports the sticky device status of a launch (GZ_OK 0, GZ_ECORRUPT 3,
+// GZ_ETIMEOUT 7) into *out (when given) and clears it, so that the next
+// launch on the same workspace starts clean.
+__global__ void k_finish(Ctl C, uint32_t* out) {
+  if (threadIdx.x == 0) {
+    const uint32_t e = ld_agent32(&C.ctrl->err);
+    if (out) *out = (e & ERRF_CORRUPT) ? 3u : (e & ERRF_TIMEOUT) ? 7u : 0u;
+    if (e) atomicAnd(&C.ctrl->err, 0u);
+  }
+}
+
 // ------------------------------------------------------------ launchers
 // Dynamic LDS: the strip staging buffer (largest strip payload + headroom).
 static size_t stage_bytes(uint32_t dtype, uint32_t tpb) {
@@ -2081,6 +2092,11 @@ hipError_t launch_fill(void* x, uint64_t n, uint32_t dtype, hipStream_t st) {
   const uint32_t grid = 4096;
   if (dtype == 0) hipLaunchKernelGGL(k_fill<float>, dim3(grid), dim3(256), 0, st, (float*)x, n);
   else hipLaunchKernelGGL(k_fill<double>, dim3(grid), dim3(256), 0, st, (double*)x, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish(const Ctl& C, uint32_t* status, hipStream_t st) {
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, st, C, status);
   return hipGetLastError();
 }
 

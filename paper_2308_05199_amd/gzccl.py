@@ -68,6 +68,7 @@ _SIGS = {
     "gz_tile_trial": ([_vp, _vp, _u64, _u32, _dbl, _vp, _vp, _vp, _vp], _i32),
     "gz_mlp_grad": ([_vp, _vp, _vp, _vp, _u64, _vp, _vp, _vp], _i32),
     "gz_mlp_adam": ([_vp, _vp, _vp, _vp, _vp, _u32, ctypes.c_float, _vp], _i32),
+    "gz_compress_noalloc": ([_vp, _u64, _i32, _dbl, _pp, _vp, _u64, _vp, _vp, _vp], _i32),
     "gz_status_str": ([_i32], ctypes.c_char_p),
 }
 for _name, (_args, _res) in _SIGS.items():
@@ -114,6 +115,18 @@ def _params(block_len=32, threads=0, grid=0, mode=0, select=0, nx=0):
 
 def bound(n, dtype=GZ_F32, block_len=32):
     return int(gz_compress_bound(n, dtype, block_len))
+
+
+def compress_noalloc(x, eb, out, out_bytes, status, block_len=32, threads=0, grid=0, mode=0,
+                     select=0, nx=0, stream=None):
+    """gz_compress without a context, for callers that cannot allocate:
+    out (uint8, at least bound() bytes), out_bytes (int64[1]) and status
+    (int32[1]) are caller-owned device tensors; nothing is allocated."""
+    p = _params(block_len, threads, grid, mode, select, nx)
+    check(gz_compress_noalloc(_ptr(x), x.numel(), _dt(x), eb, ctypes.byref(p), _ptr(out),
+                              out.numel(), _ptr(out_bytes), _ptr(status), _stream(stream)),
+          "gz_compress_noalloc")
+    return out, out_bytes
 
 
 class Context:
