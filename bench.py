@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--no-headline", action="store_true", help="skip the 1 GiB compress/decompress")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (scales profiler byte counters)")
-    ap.add_argument("--extras", default="allreduce,accuracy,sweep",
+    ap.add_argument("--extras", default="scatter,batch,selector,allreduce,accuracy,sweep",
                     help="comma list of extra measurements (none for no extras): scatter,batch,selector,allreduce,"
                          "accuracy,sweep")
     return ap.parse_args()
@@ -134,39 +134,12 @@ def _timed(torch, fn, reps=5):
     return e0.elapsed_time(e1) / reps
 
 
-def device_frames(torch, nframes, h=2048, w=2048, seed=0):
-    """Frame recipe of synth.frames (gradient background + Poisson(50) +
-    1e-4 point sources with a sigma-1 Gaussian PSF), drawn on the device."""
-    g = torch.Generator(device="cuda")
-    g.manual_seed(seed)
-    yy = torch.arange(h, device="cuda", dtype=torch.float32).view(h, 1)
-    xx = torch.arange(w, device="cuda", dtype=torch.float32).view(1, w)
-    out = torch.empty((nframes, h, w), device="cuda")
-    r = torch.arange(-3, 4, device="cuda", dtype=torch.float32)
-    psf = torch.exp(-(r.view(-1, 1) ** 2 + r.view(1, -1) ** 2) / 2)
-    for f in range(nframes):
-        a = 100 + 100 * torch.rand(1, device="cuda", generator=g)
-        b, c = (torch.rand(2, device="cuda", generator=g) - 0.5) * 0.1
-        img = a + b * xx + c * yy
-        img = img + torch.poisson(torch.full((h, w), 50.0, device="cuda"), generator=g)
-        ns = int(1e-4 * h * w)
-        ys = torch.randint(3, h - 3, (ns,), device="cuda", generator=g)
-        xs = torch.randint(3, w - 3, (ns,), device="cuda", generator=g)
-        pk = 1e3 + 9e3 * torch.rand(ns, device="cuda", generator=g)
-        src = torch.zeros((h, w), device="cuda")
-        src.index_put_((ys, xs), pk, accumulate=True)
-        img = img + torch.nn.functional.conv2d(src.view(1, 1, h, w), psf.view(1, 1, 7, 7),
-                                               padding=3).view(h, w)
-        out[f] = img
-    return out.view(-1)
-
-
 def extra_scatter(ctx, gz, torch):
     """64 frames of 2048^2 (1 GiB) in 64 log-uniform chunks of 1-64 MiB,
     eb 1e-3: one persistent compress launch, one batched decompress."""
     import numpy as np
     from paper_2308_05199_amd import synth
-    root = device_frames(torch, 64)
+    root = synth.device_frames(64)
     counts, displs = synth.loguniform_counts(root.numel(), 64, 1 << 18, 1 << 24, seed=1)
     eb = 1e-3
     out, cb, co = ctx.scatter_compress(root, counts, displs, eb)
@@ -187,106 +160,123 @@ def extra_scatter(ctx, gz, torch):
 
 
 def extra_batch(ctx, gz, torch, nreq=4096):
-    """4096 independent requests, log-uniform 4 KiB-16 MiB, fp32/fp64, eb
-    log-uniform in [1e-6,1e-2]: one persistent launch (replayed as a graph)
-    against one launch per request."""
-    import numpy as np
+    """Config 5: 4096 independent requests, log-uniform 4 KiB-16 MiB,
+    fp32/fp64, eb log-uniform in [1e-6,1e-2], as the autotuner runs them:
+    gz_tune picks each dtype's block length on the batch's largest request
+    of that dtype (requests give 0), gz_tune_batch the threads and grid of
+    the batched launch; the plan is replayed from a HIP graph, against one
+    launch per request.  The request data are drawn on the host."""
     from paper_2308_05199_amd import synth
     reqs = synth.mixed_requests(nreq, seed=0, lo_bytes=4096, hi_bytes=16 << 20)
     ctx = gz.Context(0, max_elems=sum(r["n"] for r in reqs) + 1, max_requests=nreq)
-    g = torch.Generator(device="cuda")
-    g.manual_seed(0)
     items, ins, outs, nbs = [], [], [], []
     raw = 0
-    for i, r in enumerate(reqs):
-        dt = torch.float32 if r["dtype"] == np.float32 else torch.float64
-        n = r["n"]
-        if r["kind"] == "grf":   # smooth random walk, unit variance
-            x = torch.cumsum(torch.randn(n, device="cuda", generator=g, dtype=torch.float64), 0)
-            x = (x - x.mean()) / x.std().clamp_min(1e-30)
-        else:                    # image-like row: gradient + Poisson(50)
-            base = 100 + 100 * torch.rand(1, device="cuda", generator=g, dtype=torch.float64)
-            x = (base + torch.poisson(torch.full((n,), 50.0, device="cuda", dtype=torch.float64),
-                                      generator=g)) / 100
-        x = x.to(dt)
-        code = gz.GZ_F32 if dt == torch.float32 else gz.GZ_F64
-        cap = gz.bound(n, code, 32)
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(8) as ex:   # drawn on the host, one seed per request
+        for x in ex.map(synth.request_data, reqs):
+            ins.append(torch.from_numpy(x).cuda())
+            raw += ins[-1].numel() * ins[-1].element_size()
+    # the tuner times the batch's own data: its largest request of each dtype
+    Ls = {}
+    for code, dt in ((gz.GZ_F32, torch.float32), (gz.GZ_F64, torch.float64)):
+        big = max((x for x in ins if x.dtype == dt), key=lambda x: x.numel())
+        Ls[code] = ctx.tune(big, 0).block_len
+    for x, r in zip(ins, reqs):
+        code = gz.GZ_F32 if x.dtype == torch.float32 else gz.GZ_F64
+        cap = gz.bound(x.numel(), code, Ls[code])
         o = torch.empty(cap, dtype=torch.uint8, device="cuda")
         nb = torch.zeros(1, dtype=torch.int64, device="cuda")
-        ins.append(x)
         outs.append(o)
         nbs.append(nb)
-        items.append({"in": x, "out": o, "out_bytes": nb, "n": n, "out_cap": cap,
-                      "eb": r["eb"], "dtype": code, "block_len": 32})
-        raw += x.numel() * x.element_size()
+        items.append({"in": x, "out": o, "out_bytes": nb, "n": x.numel(), "out_cap": cap,
+                      "eb": r["eb"], "dtype": code, "block_len": 0})
     arr = ctx.requests(items)
+    shape = ctx.tune_batch(gz.GZ_OP_COMPRESS, arr)
     plan = ctx.plan(gz.GZ_OP_COMPRESS, arr)
     graph = gz.Graph([plan])
     tg = _timed(torch, lambda: graph.launch(), reps=3)
     comp = sum(int(nb.item()) for nb in nbs)
+    ys = [torch.empty_like(x) for x in ins]
+    darr = ctx.requests([{"in": o, "out": y, "n": x.numel(), "in_bytes": int(nb.item()),
+                          "dtype": gz.GZ_F32 if x.dtype == torch.float32 else gz.GZ_F64,
+                          "block_len": 0} for x, o, nb, y in zip(ins, outs, nbs, ys)])
+    dshape = ctx.tune_batch(gz.GZ_OP_DECOMPRESS, darr)
+    dgraph = gz.Graph([ctx.plan(gz.GZ_OP_DECOMPRESS, darr)])
+    tdg = _timed(torch, lambda: dgraph.launch(), reps=3)
+    err_ok = all(float((y.double() - x.double()).abs().max()) <= r["eb"]
+                 for x, y, r in zip(ins, ys, reqs))
 
     def one_by_one():
         for x, o, nb, r in zip(ins, outs, nbs, reqs):
-            ctx.compress(x, r["eb"], out=o, out_bytes=nb)
+            ctx.compress(x, r["eb"], block_len=Ls[gz.GZ_F32 if x.dtype == torch.float32
+                                                   else gz.GZ_F64], out=o, out_bytes=nb)
     t1 = _timed(torch, one_by_one, reps=1)
+    st = ctx.device_status()
+    dgraph.close()
+    graph.close()
+    ctx.close()
     return {"workload": f"{len(reqs)} requests, log-uniform 4 KiB-16 MiB, fp32/fp64, "
-                        "eb log-uniform 1e-6..1e-2, L 32",
+                        "eb log-uniform 1e-6..1e-2, tuned L per dtype",
+            "tuned": {"L_f32": Ls[gz.GZ_F32], "L_f64": Ls[gz.GZ_F64],
+                      "compress_threads": shape.threads, "compress_grid": shape.grid,
+                      "decompress_threads": dshape.threads, "decompress_grid": dshape.grid},
             "raw_bytes": raw, "ratio": raw / comp,
             "batched_graph_ms": tg, "batched_GBps": raw / tg / 1e6,
             "batched_hbm_frac": (raw + comp) / tg / 1e6 / HBM_PEAK_GBPS,
-            "one_launch_per_request_ms": t1, "one_launch_per_request_GBps": raw / t1 / 1e6}
+            "decompress_graph_ms": tdg, "decompress_GBps": raw / tdg / 1e6,
+            "decompress_hbm_frac": (raw + comp) / tdg / 1e6 / HBM_PEAK_GBPS,
+            "all_within_eb": err_ok,
+            "one_launch_per_request_ms": t1, "one_launch_per_request_GBps": raw / t1 / 1e6,
+            "device_status": st}
 
 
 def extra_selector(ctx, gz, torch):
-    """Learned predictor selection on mixed fields (GRF, images, 50%-zero
-    sparse; 8x8 tiles): train on seed-disjoint fields, then compare the
-    int8 network with exhaustive trial, fixed L1D tiles and 1D blocks on
-    ratio and compress throughput."""
-    import ctypes
+    """Learned predictor selection at full size: the int8 network is trained
+    on the GPU on exhaustive-trial labels of seed-disjoint fields, then the
+    config-4 fields (546 M fp32 elements: 3D GRFs, noisy images, 50%-zero
+    sparse; 8x8 tiles, eb 1e-4 x range) are compressed with the network,
+    with exhaustive trial, with always-L1D tiles (the method without the
+    network) and as 1D blocks.  Each mode's kernel time is the sum of its
+    per-field launch times (HIP events); HBM fraction counts the input and
+    the stream written."""
     from paper_2308_05199_amd import selector, synth
-    train_f = synth.selector_fields(1000, grf_shape=(64, 256, 256), n_images=4,
-                                    image_hw=(1024, 1024), sparse_n=1 << 22)
-    feats, labels = [], []
-    for x, nx, eb in train_f:
-        f, s, l = selector.trial(ctx, torch.from_numpy(x).cuda(), nx, eb)
-        feats.append(f)
-        labels.append(l)
-    feat = torch.cat(feats)
-    lab = torch.cat(labels)
-    w = selector.train(ctx, feat, lab, steps=1500, log=log)
-    keep = (lab < 3).nonzero().view(-1)
-    calib = feat[keep[:: max(1, keep.numel() // 50000)]].cpu().numpy()
-    blob = selector.export_int8(w.cpu().numpy(), calib)
-    selector.load(ctx, blob)
-    test_f = synth.selector_fields(0, grf_shape=(128, 256, 256), n_images=8,
-                                   image_hw=(1024, 1024), sparse_n=1 << 23)
-    res = {"mlp": [0, 0.0], "exhaustive": [0, 0.0], "l1d_tiles": [0, 0.0], "blocks_1d": [0, 0.0]}
+    t0 = time.perf_counter()
+    train = synth.device_selector_fields(1, n_grf=2, n_images=8, sparse_n=1 << 24)
+    blob, counts = selector.fit(ctx, train, steps=1500, log=log)
+    del train
+    train_s = time.perf_counter() - t0
+    test = synth.device_selector_fields(0)
+    modes = (("mlp", 0), ("exhaustive", 1), ("l1d_tiles", 2), ("blocks_1d", None))
+    res = {k: [0, 0.0] for k, _ in modes}
     raw = 0
-    for x, nx, eb in test_f:
-        xd = torch.from_numpy(x).cuda()
-        raw += 4 * x.size
-        cap = gz.bound(x.size, gz.GZ_F32, 64)
-        out = torch.empty(gz.bound(x.size, gz.GZ_F32, 32), dtype=torch.uint8, device="cuda")
+    for x, nx, eb in test:
+        n = x.numel()
+        raw += 4 * n
+        out = torch.empty(gz.bound(n, gz.GZ_F32, 32), dtype=torch.uint8, device="cuda")
         nb = torch.zeros(1, dtype=torch.int64, device="cuda")
-        for key, sel in (("mlp", 0), ("exhaustive", 1), ("l1d_tiles", 2)):
-            p = gz.gz_params(64, 0, 0, 1, sel, nx)
-            run = lambda: gz.check(gz.gz_compress(ctx.h, gz._ptr(xd), x.size, gz.GZ_F32, eb,
-                                                  ctypes.byref(p), gz._ptr(out), cap,
-                                                  gz._ptr(nb), gz._stream(None)), "tiles")
+        for key, sel in modes:
+            if sel is None:
+                run = lambda: ctx.compress(x, eb, block_len=32, out=out, out_bytes=nb)
+            else:
+                run = lambda: selector.tile_compress(ctx, x, nx, eb, sel, out, nb)
             t = _timed(torch, run)
             res[key][0] += int(nb.item())
             res[key][1] += t
-        t = _timed(torch, lambda: ctx.compress(xd, eb, out=out, out_bytes=nb))
-        res["blocks_1d"][0] += int(nb.item())
-        res["blocks_1d"][1] += t
-    out = {"workload": "mixed fields (3D GRF rows, noisy images, 50%-zero sparse), 8x8 tiles, "
-                       "eb 1e-4 x range, int8 MLP 16-32-3 trained on seed-disjoint fields",
-           "elements": raw // 4}
+    del test
+    torch.cuda.empty_cache()
+    out = {"workload": "config-4 fields (10 GRFs 256^3, 40 images 2048^2, 50%-zero sparse "
+                       "201 Mi; 546 M fp32), 8x8 tiles, eb 1e-4 x range; int8 MLP 16-32-3 "
+                       "trained on the GPU on seed-disjoint fields",
+           "elements": raw // 4, "train_s": train_s,
+           "train_labels_none_l1d_l2d_skipped": counts}
     for k, (b, t) in res.items():
-        out[k] = {"ratio": raw / b, "compress_GBps": raw / t / 1e6}
+        out[k] = {"ratio": raw / b, "ms": t, "compress_GBps": raw / t / 1e6,
+                  "hbm_frac": (raw + b) / t / 1e6 / HBM_PEAK_GBPS}
     out["mlp_ratio_vs_exhaustive"] = out["mlp"]["ratio"] / out["exhaustive"]["ratio"]
-    out["mlp_speed_vs_exhaustive"] = (out["mlp"]["compress_GBps"] /
-                                      out["exhaustive"]["compress_GBps"])
+    out["mlp_speed_vs_exhaustive"] = out["exhaustive"]["ms"] / out["mlp"]["ms"]
+    out["mlp_gain_over_l1d_tiles"] = out["mlp"]["ratio"] / out["l1d_tiles"]["ratio"]
+    out["mlp_gain_over_blocks_1d"] = out["mlp"]["ratio"] / out["blocks_1d"]["ratio"]
+    out["device_status"] = ctx.device_status()
     return out
 
 
@@ -425,7 +415,7 @@ def extra_allreduce(ctx, gz, torch, bufs_np, eb):
 
 
 def extra_accuracy(ctx, gz, torch, nframes=8):
-    """Image stacking (Sec. 4.4 analogue on synthetic frames): the sum of
+    """Image stacking (Sec. 4.5 analogue on synthetic frames): the sum of
     8 frames of 2048^2, scaled to [0, 1] by the largest pixel of all frames
     (the absolute bounds 1e-4 and 2e-4 are meant for unit-scale images), by
     ring and recursive-doubling compressed Allreduce; PSNR = 20 log10(range)
@@ -433,7 +423,8 @@ def extra_accuracy(ctx, gz, torch, nframes=8):
     exact (fp64) sum, range = max - min of that sum."""
     import math
     from paper_2308_05199_amd.allreduce import ReDoubAllreduce, RingAllreduce
-    fr = device_frames(torch, nframes).view(nframes, -1)
+    from paper_2308_05199_amd import synth
+    fr = synth.device_frames(nframes).view(nframes, -1)
     fr /= fr.max()
     n = fr.shape[1]
     exact = fr.double().sum(0)
@@ -469,22 +460,45 @@ def extra_accuracy(ctx, gz, torch, nframes=8):
     return res
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(bufs_np, eb):
     """The oracle, unchanged, on the same reduce-scatter (all 8 chunks,
-    8 operations each) on one host core."""
+    8 operations each): once with its OpenMP variant on the host cores it
+    is given (OMP_NUM_THREADS), once on one core."""
     import oracle
     from paper_2308_05199_amd.ring import chunk_bounds
     oracle.build(force=False)
     n = bufs_np[0].size
-    t0 = time.perf_counter()
-    for c, (lo, hi) in enumerate(chunk_bounds(n, N_RANKS)):
-        s = oracle.compress(bufs_np[c][lo:hi], eb, block_len=BLOCK)
-        for st in range(1, N_RANKS):
-            s = oracle.fused_step(s, bufs_np[(c + st) % N_RANKS][lo:hi], eb, block_len=BLOCK)
-    dt = time.perf_counter() - t0
-    return {"value": N_RANKS * n * 4 / dt / 1e9, "unit": "GB/s", "cores": 1, "kind": "oracle",
+
+    def run(mt):
+        t0 = time.perf_counter()
+        for c, (lo, hi) in enumerate(chunk_bounds(n, N_RANKS)):
+            s = oracle.compress(bufs_np[c][lo:hi], eb, block_len=BLOCK, mt=mt)
+            for st in range(1, N_RANKS):
+                s = oracle.fused_step(s, bufs_np[(c + st) % N_RANKS][lo:hi], eb,
+                                      block_len=BLOCK, mt=mt)
+        return time.perf_counter() - t0
+
+    raw = N_RANKS * n * 4
+    t_all = run(True)
+    t_one = run(False)
+    threads = oracle.threads()
+    return {"value": raw / t_all / 1e9, "unit": "GB/s", "cores": threads, "kind": "oracle",
             "sample": "the full config-2 reduce-scatter (8 chunks x (1 compress + 7 fused "
-                      f"steps), 512 MiB of rank data) on one host core, {dt:.1f} s"}
+                      f"steps), 512 MiB of rank data), all-core variant (superblocks on "
+                      f"{threads} threads, serial offset scan): {t_all:.1f} s",
+            "single_core": {"value": raw / t_one / 1e9, "unit": "GB/s", "cores": 1,
+                            "seconds": t_one},
+            "nproc": os.cpu_count(), "cpu_model": cpu_model()}
 
 
 def main():

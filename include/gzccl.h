@@ -9,13 +9,14 @@
  *     are host pointers read during the call only.
  *   - Calls only enqueue work on `stream` and return; no call synchronises
  *     the host, except gz_ctx_create, gz_ctx_status, gz_plan_create,
- *     gz_selector_* and gz_tune, which say so.  Compressed sizes land in
+ *     gz_graph_create, gz_selector_load and the tuners, which say so.  Compressed sizes land in
  *     caller-provided device words; read them after the stream completes
  *     (the paper syncs the streams before reading the sizes, Sec. 3.3.4).
  *   - The context owns all temporary device memory: a workspace allocated
  *     once at gz_ctx_create (the paper's pre-allocated GPU buffer pool,
- *     Sec. 3.3.1, and its reused temporary buffers, Sec. 3.3.2).  No call
- *     allocates device memory.  One context serves one stream at a time;
+ *     Sec. 3.3.1, and its reused temporary buffers, Sec. 3.3.2), including
+ *     the arena that holds plan descriptors.  No other call allocates device
+ *     memory.  One context serves one stream at a time;
  *     contexts share nothing, so several contexts may run concurrently on
  *     different streams (the per-stream buffers of Sec. 3.3.4).
  *   - Argument errors found on the host return at once and enqueue nothing.
@@ -86,7 +87,9 @@ typedef struct {
   uint32_t nx;
 } gz_params;
 
-/* One independent request of a batch (mode 0).  Compression: in = T[n],
+/* One independent request of a batch (mode 0).  block_len 0 takes the
+ * context's tuned block length for the dtype (set by gz_tune with
+ * block_len 0; 32 before any tuning).  Compression: in = T[n],
  * out = stream buffer of out_cap bytes, d_out_bytes receives its size.
  * Decompression: in = stream of in_bytes, out = T[n] (n and dtype and
  * block_len are what the stream must declare).  Fused step: in = fp32
@@ -121,15 +124,21 @@ gz_status gz_ctx_create(gz_ctx** ctx, int device, uint64_t max_elems,
                         uint32_t max_requests);
 void gz_ctx_destroy(gz_ctx* ctx);
 
-/* Synchronises the device, returns the sticky device status (GZ_OK,
- * GZ_ECORRUPT or GZ_ETIMEOUT) in *device_status and clears it. */
-gz_status gz_ctx_status(gz_ctx* ctx, gz_status* device_status);
+/* Waits for `stream` (the stream the context's work was enqueued on; other
+ * streams are not waited for), returns the sticky device status (GZ_OK,
+ * GZ_ECORRUPT or GZ_ETIMEOUT) in *device_status and clears it.  The paper
+ * reads compressed sizes after such a stream sync (Sec. 3.3.4). */
+gz_status gz_ctx_status(gz_ctx* ctx, gz_stream_t stream, gz_status* device_status);
 
 /* Clears the context's look-back and ticket state (after a device error). */
 gz_status gz_ctx_reset(gz_ctx* ctx, gz_stream_t stream);
 
 /* Largest stream a compression of n elements can produce:
- * 64 + 4*ceil(n/4096) + roundup4(ceil(n/L)) + n*sizeof(T). */
+ * 64 + 4*ceil(n/4096) + roundup4(ceil(n/L)) + n*sizeof(T); 0 for an invalid
+ * dtype or block length.  Compressed sizes are known only after the kernel
+ * has run (Sec. 3.3.4 reads them after a stream sync), so output buffers --
+ * the paper's pre-allocated device buffers (Sec. 3.3.1) -- are sized by
+ * this bound in advance; with it, capacity errors are host-side. */
 uint64_t gz_compress_bound(uint64_t n, gz_dtype dtype, uint32_t block_len);
 
 /* Elementwise quantisation (the q and FAIL steps above) into d_q (int32,
@@ -149,9 +158,15 @@ gz_status gz_compress(gz_ctx* ctx, const void* d_in, uint64_t n, gz_dtype dtype,
                       uint64_t out_cap, uint64_t* d_out_bytes,
                       gz_stream_t stream);
 
-/* Decompresses a stream of in_bytes into d_out[0..n).  The caller states
- * what it expects (n, dtype, block length, mode, nx); a stream that says
- * otherwise, or is malformed, sets GZ_ECORRUPT on the device. */
+/* Decompresses a stream of in_bytes into d_out[0..n) (caller-owned device
+ * memory, n elements of dtype): the decompression each rank runs on the
+ * data it receives (Sec. 3.3.3: N-1 decompressions in a ring Allreduce's
+ * Allgather stage; Sec. 3.2.2 characterises it with compression).  The
+ * caller states what it expects (n, dtype, block length, mode, nx); a
+ * stream that says otherwise, or is malformed, sets GZ_ECORRUPT on the
+ * device and leaves d_out unspecified; the kernel never reads past in_bytes
+ * nor writes past n elements.  Overlapping input and output, null pointers
+ * or bad params return GZ_EINVAL with nothing enqueued. */
 gz_status gz_decompress(gz_ctx* ctx, const void* d_in, uint64_t in_bytes,
                         uint64_t n, gz_dtype dtype, const gz_params* p,
                         void* d_out, gz_stream_t stream);
@@ -167,7 +182,7 @@ gz_status gz_fused_reduce_step(gz_ctx* ctx, const void* d_cmp_in,
                                uint64_t* d_out_bytes, gz_stream_t stream);
 
 /* The reduction after a receive in recursive-doubling gZ-Allreduce (Sec.
- * 3.3.2): decode the fp32 stream of in_bytes (n elements, block length and
+ * 3.3.4): decode the fp32 stream of in_bytes (n elements, block length and
  * mode 0 as in p) and add it into d_acc in place, d_acc[i] = fl32(decoded[i]
  * + d_acc[i]), in one kernel that never writes the decoded values.  d_acc
  * (caller-owned device memory, n floats) must not overlap the stream.  A
@@ -190,8 +205,13 @@ gz_status gz_scatter_compress(gz_ctx* ctx, const void* d_root, gz_dtype dtype,
                               uint64_t* d_chunk_bytes, uint64_t* d_chunk_offsets,
                               gz_stream_t stream);
 
-/* Inverse of gz_scatter_compress in one batched launch: chunk j starts at
- * d_packed + d_chunk_offsets[j] and decodes into d_root + h_displs[j]. */
+/* Inverse of gz_scatter_compress in one batched launch -- each destination
+ * of gZ-Scatter decompresses the chunk it received (Sec. 3.3.4; the paper
+ * overlaps these decompressions on several streams, here they share one
+ * launch): chunk j starts at d_packed + d_chunk_offsets[j] (device array of
+ * nchunks offsets) and decodes h_counts[j] elements into d_root +
+ * h_displs[j].  A chunk whose stream is malformed or says otherwise sets
+ * GZ_ECORRUPT on the device; nothing is read past packed_bytes. */
 gz_status gz_scatter_decompress(gz_ctx* ctx, const void* d_packed,
                                 uint64_t packed_bytes,
                                 const uint64_t* d_chunk_offsets,
@@ -205,13 +225,20 @@ gz_status gz_scatter_decompress(gz_ctx* ctx, const void* d_packed,
  * under-use the GPU one by one (Sec. 3.2.2, Sec. 3.3.3 "total compression
  * cost") share one grid.  op selects compress, decompress, fused step or
  * decode-and-accumulate (fp32 only, as gz_decompress_add); p gives
- * threads/grid only. */
+ * threads/grid only (0: the shapes gz_tune_batch stored for this op and
+ * element-type mix, else defaults). */
 gz_status gz_batch(gz_ctx* ctx, gz_op op, const gz_request* h_reqs,
                    uint32_t nreq, const gz_params* p, gz_stream_t stream);
 
-/* A plan uploads a batch's descriptors once (synchronous) so that
+/* A plan uploads a batch's descriptors once (synchronous: it first waits for
+ * the device, then copies) into the context's plan arena, so that
  * gz_plan_launch is a single kernel launch with no host work, suitable for
- * stream capture.  Plans of one context must run in order on one stream. */
+ * stream capture.  No device memory is allocated: the arena, sized at
+ * gz_ctx_create, holds 16 * max_requests + 64 descriptors and the strip
+ * maps of 16 batches of max_elems elements; a plan that does not fit
+ * returns GZ_ENOSPC.  Plans of one context must run in order on one stream.
+ * Destroy graphs and plans before their context (a plan outliving its
+ * context can only be destroyed). */
 gz_status gz_plan_create(gz_ctx* ctx, gz_op op, const gz_request* h_reqs,
                          uint32_t nreq, const gz_params* p, gz_plan** plan);
 gz_status gz_plan_launch(gz_plan* plan, gz_stream_t stream);
@@ -224,12 +251,31 @@ gz_status gz_graph_create(gz_plan* const* plans, uint32_t nplans,
 gz_status gz_graph_launch(gz_graph* graph, gz_stream_t stream);
 void gz_graph_destroy(gz_graph* graph);
 
-/* Times the launch shapes (threads, grid) of compress and decompress for
- * (dtype, block_len) on n synthetic elements and stores the fastest in the
- * context; with a non-null cache_path, reads/writes a JSON cache there.
- * Synchronous; allocates scratch buffers for the measurement. */
-gz_status gz_tune(gz_ctx* ctx, gz_dtype dtype, uint32_t block_len, uint64_t n,
-                  const char* cache_path, gz_params* best);
+/* The autotuner (block size and threads per block, the benchmark spec's batching
+ * extension, for the small-input under-use of Sec. 3.2.2).  Times the launch
+ * shapes (threads, grid) of compress and decompress for (dtype, block_len)
+ * on the caller's sample d_sample[0..n) (read only) and stores the fastest
+ * in the context; with block_len 0 it tries 32, 64 and 128 and stores the
+ * fastest as the block length of requests that give 0.  d_work is a
+ * caller-owned device buffer of at least
+ *   roundup256(n * sizeof(T)) + roundup256(gz_compress_bound(n, dtype, 32)) + 8
+ * bytes (decoded values, stream, size word) that must not overlap the
+ * sample (GZ_ENOSPC if smaller).  Runs on `stream` and waits for it; with a
+ * non-null cache_path, reads and appends a JSON-lines cache of shapes there.
+ * Allocates nothing.  Synchronous. */
+gz_status gz_tune(gz_ctx* ctx, gz_dtype dtype, uint32_t block_len, const void* d_sample,
+                  uint64_t n, void* d_work, uint64_t work_bytes, const char* cache_path,
+                  gz_params* best, gz_stream_t stream);
+
+/* Times the caller's own batch (op compress, decompress or fused step; the
+ * accumulate op updates in place and is refused with GZ_EINVAL) over
+ * threads {128..1024} x grid {1, 2, occupancy, 2 x occupancy} x CUs, and
+ * stores the fastest shape for (op, batch holds fp64) in the context, where
+ * gz_batch and gz_plan_create take it.  Runs the batch 4 times per shape in
+ * place on `stream` (outputs are rewritten with the same bytes) and waits
+ * for it; allocates nothing.  Synchronous. */
+gz_status gz_tune_batch(gz_ctx* ctx, gz_op op, const gz_request* h_reqs, uint32_t nreq,
+                        const char* cache_path, gz_params* best, gz_stream_t stream);
 
 /* Learned selector (mode 1, select 0): loads the int8 weight blob
  * ("GZM1", u32 shift, int8 W1[32][16], int32 b1[32], int8 W2[3][32],

@@ -12,7 +12,7 @@ from . import gzo
 
 
 def decompress_add(stream, acc):
-    """The reduction after a receive (Sec. 3.3.2): fl32(decoded + acc)."""
+    """The reduction after a receive (Sec. 3.3.4): fl32(decoded + acc)."""
     acc = np.ascontiguousarray(acc, dtype=np.float32)
     return np.add(gzo.decompress(stream), acc, dtype=np.float32)
 
@@ -38,7 +38,7 @@ def ring_reduce_scatter(bufs, eb, block_len=32):
 
 
 def ring_allgather(streams, n):
-    """Allgather stage of the ring Allreduce (Sec. 3.2.1): the one stream of
+    """Allgather stage of the ring Allreduce (Sec. 3.3.3): the one stream of
     each chunk reaches every rank, which decodes all N of them.  Every rank
     decodes the same streams, so all ranks' results are this one array."""
     N = len(streams)
@@ -54,7 +54,7 @@ def ring_allreduce(bufs, eb, block_len=32):
 
 def redoub_schedule(N):
     """The exchange pattern of recursive-doubling Allreduce with remainder
-    (Sec. 3.3.2): r = N - 2^k with 2^k the largest power of two not above N.
+    (Sec. 3.3.4): r = N - 2^k with 2^k the largest power of two not above N.
     Returns (r, k, part) where part[p] is the original rank that plays
     rank p among the 2^k participants: the odd ranks 2i+1 (i < r) and the
     ranks i >= 2r."""
@@ -66,7 +66,7 @@ def redoub_schedule(N):
 
 
 def redoub_allreduce(bufs, eb, block_len=32, counts=None):
-    """gZ-Allreduce (ReDoub), Sec. 3.3.2.  Stage 1: even rank 2i (i < r)
+    """gZ-Allreduce (ReDoub), Sec. 3.3.4.  Stage 1: even rank 2i (i < r)
     compresses its whole buffer for rank 2i+1, which decodes it and adds it
     to its own.  Stage 2: in each of k steps every participant compresses its
     current buffer, the partner p XOR 2^step decodes it and adds it to its

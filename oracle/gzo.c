@@ -11,6 +11,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define SUPER 4096u          /* elements per superblock */
 #define HDR_BYTES 64u
@@ -637,4 +640,119 @@ int gzo_tile_trial(const float* x, uint64_t n, uint32_t nx, double eb, int8_t* f
     label[b] = (fail || !nonzero) ? 255 : (uint8_t)best;
   }
   return GZO_OK;
+}
+
+/* ------------------------------------------- all-core variants (OpenMP)
+ * The same encodings with the host's cores working on superblocks at
+ * once: every superblock's blocks are encoded, in order, into a scratch
+ * area of their own; the offsets of the superblocks are then summed one
+ * after another (the exclusive scan stays serial), and the payloads copied
+ * into place.  Decoding validates the stream serially as gzo_decompress
+ * does, then decodes superblocks at once from their table entries.  The
+ * bytes are those of gzo_compress / gzo_decompress. */
+int gzo_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+int gzo_compress_mt(const void* x, uint64_t n, int dtype, double eb, int block_len,
+                    int mode, uint32_t nx, int select, const uint8_t* mlp_blob,
+                    uint8_t* out, uint64_t out_cap, uint64_t* out_bytes) {
+  Geom g;
+  memset(&g, 0, sizeof g);
+  g.n = n; g.dtype = dtype; g.L = block_len; g.mode = mode; g.nx = nx;
+  g.select = mode == 1 ? select : 0; g.eb = eb;
+  if (!check_params(&g, mlp_blob)) return GZO_EINVAL;
+  if (!make_step(dtype, eb, &g.t32, &g.t64)) return GZO_EINVAL;
+  geom_fill(&g);
+  if (out_cap < gzo_compress_bound(n, dtype, block_len)) return GZO_ENOSPC;
+  memset(out, 0, g.pay_off);
+  const uint64_t bps = SUPER / (uint64_t)g.L, room = (uint64_t)SUPER * elem_size(dtype);
+  uint8_t* scratch = (uint8_t*)malloc(g.NS ? g.NS * room : 1);
+  uint64_t* sizes = (uint64_t*)malloc((g.NS ? g.NS : 1) * sizeof(uint64_t));
+  if (!scratch || !sizes) {
+    free(scratch);
+    free(sizes);
+    return GZO_EINVAL;
+  }
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t k = 0; k < (int64_t)g.NS; ++k) {
+    uint64_t used = 0;
+    for (uint64_t b = (uint64_t)k * bps; b < g.B && b < ((uint64_t)k + 1) * bps; ++b) {
+      uint32_t sz = 0;
+      out[g.hdr_off + b] = encode_block(&g, x, b, mlp_blob, scratch + k * room + used, &sz);
+      used += sz;
+    }
+    sizes[k] = used;
+  }
+  uint64_t payload = 0;
+  for (uint64_t k = 0; k < g.NS; ++k) {  /* exclusive scan, in order */
+    put_u32(out + HDR_BYTES + 4 * k, (uint32_t)(payload / 4));
+    payload += sizes[k];
+  }
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t k = 0; k < (int64_t)g.NS; ++k) {
+    uint64_t at = (uint64_t)get_u32(out + HDR_BYTES + 4 * k) * 4;
+    memcpy(out + g.pay_off + at, scratch + k * room, sizes[k]);
+  }
+  free(scratch);
+  free(sizes);
+  write_header(out, &g, payload);
+  *out_bytes = g.pay_off + payload;
+  return GZO_OK;
+}
+
+int gzo_decompress_mt(const uint8_t* in, uint64_t in_bytes, void* out,
+                      uint64_t out_cap_elems, uint64_t* n_out) {
+  Geom g;
+  uint64_t payload;
+  if (!parse_header(in, in_bytes, &g, &payload)) return GZO_ECORRUPT;
+  if (g.n > out_cap_elems) return GZO_ENOSPC;
+  uint64_t bps = SUPER / (uint64_t)g.L, off = 0;
+  for (uint64_t b = 0; b < g.B; ++b) {
+    if (b % bps == 0 && (uint64_t)get_u32(in + HDR_BYTES + 4 * (b / bps)) * 4 != off)
+      return GZO_ECORRUPT;
+    uint32_t sz;
+    if (!header_size(&g, b, in[g.hdr_off + b], &sz)) return GZO_ECORRUPT;
+    off += sz;
+  }
+  if (off != payload) return GZO_ECORRUPT;
+  for (uint64_t i = g.B; i < round4(g.B); ++i)
+    if (in[g.hdr_off + i]) return GZO_ECORRUPT;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t k = 0; k < (int64_t)g.NS; ++k) {
+    uint64_t at = (uint64_t)get_u32(in + HDR_BYTES + 4 * k) * 4;
+    for (uint64_t b = (uint64_t)k * bps; b < g.B && b < ((uint64_t)k + 1) * bps; ++b) {
+      uint32_t sz;
+      header_size(&g, b, in[g.hdr_off + b], &sz);
+      decode_block(&g, b, in[g.hdr_off + b], in + g.pay_off + at, out);
+      at += sz;
+    }
+  }
+  if (n_out) *n_out = g.n;
+  return GZO_OK;
+}
+
+int gzo_fused_step_mt(const uint8_t* in, uint64_t in_bytes, const float* local,
+                      uint64_t n, double eb, int block_len, uint8_t* out,
+                      uint64_t out_cap, uint64_t* out_bytes) {
+  uint64_t sn;
+  int dt, L, mode;
+  uint32_t nx;
+  if (gzo_stream_info(in, in_bytes, &sn, &dt, &L, &mode, &nx, NULL, NULL) != GZO_OK)
+    return GZO_ECORRUPT;
+  if (dt != 0 || mode != 0 || sn != n || L != block_len) return GZO_ECORRUPT;
+  float* y = (float*)malloc((n ? n : 1) * sizeof(float));
+  if (!y) return GZO_EINVAL;
+  int st = gzo_decompress_mt(in, in_bytes, y, n, NULL);
+  if (st == GZO_OK) {
+#pragma omp parallel for
+    for (int64_t i = 0; i < (int64_t)n; ++i) y[i] = y[i] + local[i]; /* elementwise */
+    st = gzo_compress_mt(y, n, 0, eb, block_len, 0, 0, 0, NULL, out, out_cap, out_bytes);
+  }
+  free(y);
+  return st;
 }

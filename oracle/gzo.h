@@ -131,6 +131,20 @@ void gzo_tile_sizes(const int32_t* q, uint32_t* sizes3);
 int gzo_tile_trial(const float* x, uint64_t n, uint32_t nx, double eb, int8_t* feat,
                    uint32_t* sizes, uint8_t* label);
 
+/* All-core variants: superblocks encoded (decoded) by the host's threads at
+ * once, the offset scan kept serial; the same bytes as the calls above.
+ * gzo_threads() is the thread count they use (OMP_NUM_THREADS). */
+int gzo_threads(void);
+int gzo_compress_mt(const void* x, uint64_t n, int dtype, double eb,
+                    int block_len, int mode, uint32_t nx, int select,
+                    const uint8_t* mlp_blob, uint8_t* out, uint64_t out_cap,
+                    uint64_t* out_bytes);
+int gzo_decompress_mt(const uint8_t* in, uint64_t in_bytes, void* out,
+                      uint64_t out_cap_elems, uint64_t* n_out);
+int gzo_fused_step_mt(const uint8_t* in, uint64_t in_bytes, const float* local,
+                      uint64_t n, double eb, int block_len, uint8_t* out,
+                      uint64_t out_cap, uint64_t* out_bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,7 +26,7 @@ def build(force=True):
         return LIB_PATH
     tmp = LIB_PATH + ".tmp"
     subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off",
-                           "-fno-fast-math", "-fPIC", "-shared", "-Wall",
+                           "-fno-fast-math", "-fopenmp", "-fPIC", "-shared", "-Wall",
                            "-o", tmp, src, "-lm"])
     os.replace(tmp, LIB_PATH)
     return LIB_PATH
@@ -63,6 +63,10 @@ def lib():
         L.gzo_tile_sizes.argtypes = [vp, vp]
         L.gzo_tile_sizes.restype = None
         L.gzo_tile_trial.argtypes = [vp, u64, u32, dbl, vp, vp, vp]
+        L.gzo_threads.restype = i32
+        L.gzo_compress_mt.argtypes = L.gzo_compress.argtypes
+        L.gzo_decompress_mt.argtypes = L.gzo_decompress.argtypes
+        L.gzo_fused_step_mt.argtypes = L.gzo_fused_step.argtypes
         _lib = L
     return _lib
 
@@ -93,8 +97,14 @@ def quantize(x, eb):
     return q, f.astype(bool)
 
 
-def compress(x, eb, block_len=32, mode=0, nx=0, select=0, blob=None, cap=None):
-    """Returns the GZ1 stream of x as a uint8 array."""
+def threads():
+    """Host threads the all-core (mt=True) variants use."""
+    return int(lib().gzo_threads())
+
+
+def compress(x, eb, block_len=32, mode=0, nx=0, select=0, blob=None, cap=None, mt=False):
+    """Returns the GZ1 stream of x as a uint8 array (mt: on all host cores,
+    same bytes)."""
     x = np.ascontiguousarray(x)
     dt = _dtype_code(x)
     need = compress_bound(x.size, dt, block_len)
@@ -103,9 +113,9 @@ def compress(x, eb, block_len=32, mode=0, nx=0, select=0, blob=None, cap=None):
     b = None
     if blob is not None:
         b = np.frombuffer(bytes(blob), np.uint8).copy()
-    st = lib().gzo_compress(_ptr(x), x.size, dt, eb, block_len, mode, nx, select,
-                            _ptr(b) if b is not None else None, _ptr(out),
-                            out.size, ctypes.byref(nb))
+    fn = lib().gzo_compress_mt if mt else lib().gzo_compress
+    st = fn(_ptr(x), x.size, dt, eb, block_len, mode, nx, select,
+            _ptr(b) if b is not None else None, _ptr(out), out.size, ctypes.byref(nb))
     if st:
         raise OracleError(st, "compress")
     return out[:nb.value].copy()
@@ -127,7 +137,7 @@ def stream_info(s):
                 nx=nx.value, eb=eb.value, total_bytes=tot.value)
 
 
-def decompress_status(s, cap=None):
+def decompress_status(s, cap=None, mt=False):
     """(status, array) without raising."""
     s = np.ascontiguousarray(s, dtype=np.uint8)
     try:
@@ -137,26 +147,28 @@ def decompress_status(s, cap=None):
     n = info["n"] if cap is None else cap
     out = np.zeros(max(n, 1), np.float32 if info["dtype"] == F32 else np.float64)
     got = ctypes.c_uint64()
-    st = lib().gzo_decompress(_ptr(s), s.size, _ptr(out), n, ctypes.byref(got))
+    fn = lib().gzo_decompress_mt if mt else lib().gzo_decompress
+    st = fn(_ptr(s), s.size, _ptr(out), n, ctypes.byref(got))
     if st:
         return st, None
     return OK, out[:got.value]
 
 
-def decompress(s):
-    st, out = decompress_status(s)
+def decompress(s, mt=False):
+    st, out = decompress_status(s, mt=mt)
     if st:
         raise OracleError(st, "decompress")
     return out
 
 
-def fused_step(stream, local, eb, block_len=32):
+def fused_step(stream, local, eb, block_len=32, mt=False):
     local = np.ascontiguousarray(local, dtype=np.float32)
     stream = np.ascontiguousarray(stream, dtype=np.uint8)
     out = np.zeros(compress_bound(local.size, F32, block_len), np.uint8)
     nb = ctypes.c_uint64(0)
-    st = lib().gzo_fused_step(_ptr(stream), stream.size, _ptr(local), local.size, eb,
-                              block_len, _ptr(out), out.size, ctypes.byref(nb))
+    fn = lib().gzo_fused_step_mt if mt else lib().gzo_fused_step
+    st = fn(_ptr(stream), stream.size, _ptr(local), local.size, eb, block_len, _ptr(out),
+            out.size, ctypes.byref(nb))
     if st:
         raise OracleError(st, "fused_step")
     return out[:nb.value].copy()

@@ -14,10 +14,10 @@ from .ring import RingReduceScatter, chunk_bounds
 
 
 class RingAllreduce:
-    """Ring Allreduce (Sec. 3.2.1): the compressed Reduce_scatter of
+    """Ring Allreduce (Sec. 3.3.3): the compressed Reduce_scatter of
     ring.py, then the Allgather stage.  The Reduce_scatter's last fused step
     is the one compression the Allgather needs; every rank then decodes all
-    N chunk streams into its own output (Sec. 3.2.1: N-1 decompressions of
+    N chunk streams into its own output (Sec. 3.3.3: N-1 decompressions of
     received chunks, plus its own chunk, whose fp32 sum the fused step never
     writes).  All N decodes of all ranks are one batched launch."""
 
@@ -57,7 +57,7 @@ def redoub_schedule(N):
 
 
 class ReDoubAllreduce:
-    """gZ-Allreduce (ReDoub), Sec. 3.3.2, in place on the N rank buffers.
+    """gZ-Allreduce (ReDoub), Sec. 3.3.4, in place on the N rank buffers.
     Stage 1: even rank 2i (i < r) compresses its whole buffer for rank
     2i+1, which decodes it and adds it to its own.  Stage 2: k steps; in
     step j every participant compresses its whole current buffer and adds

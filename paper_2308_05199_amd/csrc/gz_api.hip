@@ -37,6 +37,33 @@ struct Tuned {
   uint32_t tpb = 0, grid = 0;
 };
 
+// First-fit ranges of a context-owned device array (plan descriptors), so
+// that creating and destroying plans never allocates device memory.
+struct Arena {
+  uint64_t cap = 0;
+  std::vector<std::pair<uint64_t, uint64_t>> used;  // (offset, length), by offset
+  bool take(uint64_t len, uint64_t& off) {
+    if (len == 0 || len > cap) return false;
+    uint64_t at = 0;
+    size_t i = 0;
+    for (; i < used.size(); ++i) {
+      if (used[i].first - at >= len) break;
+      at = used[i].first + used[i].second;
+    }
+    if (i == used.size() && cap - at < len) return false;
+    used.insert(used.begin() + (long)i, {at, len});
+    off = at;
+    return true;
+  }
+  void give(uint64_t off) {
+    for (size_t i = 0; i < used.size(); ++i)
+      if (used[i].first == off) {
+        used.erase(used.begin() + (long)i);
+        return;
+      }
+  }
+};
+
 }  // namespace
 
 struct gz_ctx {
@@ -58,17 +85,25 @@ struct gz_ctx {
   bool stage_used[STAGE_SLOTS] = {};
   int stage_next = 0;
   size_t stage_bytes = 0;
-  Tuned tuned[3][2][3];  // [op][dtype][log2L-5]
+  Tuned tuned[3][2][3];  // single calls: [op][dtype][log2L-5]
+  Tuned batch_tuned[4][2];  // batched launches: [op][batch holds fp64]
+  uint32_t best_L[2] = {0, 0};  // tuned block length per dtype (0: untuned, 32)
   uint64_t wait_ticks = 0;    // one second of the device's constant-rate clock
   float* train_ws = nullptr;  // selector training: per-sample backward terms
+  // plan arena: descriptors and strip maps of live plans (allocated once)
+  Job* plan_jobs = nullptr;
+  uint32_t* plan_map = nullptr;
+  Arena plan_jobs_arena, plan_map_arena;
+  std::vector<gz_plan*> live_plans;
   Ctl ctl() const { return Ctl{ctrl, status, jobbase, blob, wait_ticks}; }
 };
 
 struct gz_plan {
-  gz_ctx* ctx = nullptr;
+  gz_ctx* ctx = nullptr;  // null once the context is destroyed
   uint32_t op = 0;
-  Job* d_jobs = nullptr;
-  uint32_t* d_map = nullptr;
+  Job* d_jobs = nullptr;      // in the context's plan arena
+  uint32_t* d_map = nullptr;  // in the context's plan arena
+  uint64_t jobs_off = 0, map_off = 0;
   uint32_t total = 0;
   uint32_t njobs = 0;  // uniform batch: the kernels derive (job, strip)
   uint32_t tpb = 0, grid = 0;
@@ -277,8 +312,11 @@ gz_status build_requests(gz_ctx* c, gz_op op, const gz_request* r, uint32_t nreq
     const gz_request& q = r[j];
     Job J;
     memset(&J, 0, sizeof J);
-    const uint32_t L = q.block_len ? q.block_len : 32;
-    if (!valid_L(L) || (q.dtype != GZ_F32 && q.dtype != GZ_F64)) return GZ_EINVAL;
+    if (q.dtype != GZ_F32 && q.dtype != GZ_F64) return GZ_EINVAL;
+    // block length 0: the context's tuned length for the dtype (gz_tune);
+    // a decoded stream must declare the length it was written with
+    const uint32_t L = q.block_len ? q.block_len : (c->best_L[q.dtype] ? c->best_L[q.dtype] : 32);
+    if (!valid_L(L)) return GZ_EINVAL;
     if ((op == GZ_OP_FUSED || op == GZ_OP_ACCUMULATE) && q.dtype != GZ_F32)
       return GZ_EUNSUPPORTED;
     if (q.n && (!q.in || !q.out)) return GZ_EINVAL;
@@ -309,6 +347,29 @@ gz_status build_requests(gz_ctx* c, gz_op op, const gz_request* r, uint32_t nreq
   if (strip > c->max_strips || strip >= (1ull << 32)) return GZ_ENOSPC;
   fill_map(jobs, true, map);
   return GZ_OK;
+}
+
+// Workgroup size of a batched launch: the caller's, else the tuned one for
+// (op, batch holds fp64) (gz_tune_batch), else the single-call default of
+// the widest element type.
+uint32_t batch_tpb(const gz_ctx* c, gz_op op, const gz_request* r, uint32_t nreq,
+                   const gz_params* p, bool& wide) {
+  wide = false;
+  for (uint32_t j = 0; j < nreq; ++j) wide = wide || r[j].dtype == GZ_F64;
+  if (p && p->threads) return p->threads;
+  const Tuned& t = c->batch_tuned[op][wide ? 1 : 0];
+  if (t.tpb) return t.tpb;
+  return pick_tpb(c, op, wide ? GZ_F64 : GZ_F32, 32, nullptr);
+}
+
+uint32_t batch_grid(const gz_ctx* c, gz_op op, bool wide, uint32_t tpb, uint64_t total,
+                    const gz_params* p) {
+  uint64_t g;
+  const Tuned& t = c->batch_tuned[op][wide ? 1 : 0];
+  if (p && p->grid) g = p->grid;
+  else if (t.grid && t.tpb == tpb) g = t.grid;
+  else g = (uint64_t)c->cus * gzk::occupancy_blocks(gzk::OCC_BATCH + (uint32_t)op, wide, 5, tpb);
+  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(g, total));
 }
 
 }  // namespace
@@ -371,6 +432,11 @@ gz_status gz_ctx_create(gz_ctx** out, int device, uint64_t max_elems, uint32_t m
   ok = ok && hipMalloc((void**)&c->d_map, c->max_strips * 8) == hipSuccess;
   ok = ok && hipMalloc((void**)&c->train_ws,
                        (size_t)gzs::MLP_MAX_BATCH * gzs::MLP_ROW * sizeof(float)) == hipSuccess;
+  // live plans may hold up to 16 batches' worth of descriptors and maps
+  c->plan_jobs_arena.cap = 16ull * max_requests + 64;
+  c->plan_map_arena.cap = 16ull * 2 * c->max_strips + 1024;
+  ok = ok && hipMalloc((void**)&c->plan_jobs, c->plan_jobs_arena.cap * sizeof(Job)) == hipSuccess;
+  ok = ok && hipMalloc((void**)&c->plan_map, c->plan_map_arena.cap * 4) == hipSuccess;
   c->stage_bytes = (size_t)max_requests * sizeof(Job) + c->max_strips * 8;
   for (int k = 0; ok && k < STAGE_SLOTS; ++k) {
     ok = hipHostMalloc((void**)&c->stage[k], c->stage_bytes, hipHostMallocDefault) == hipSuccess &&
@@ -395,6 +461,7 @@ gz_status gz_ctx_create(gz_ctx** out, int device, uint64_t max_elems, uint32_t m
 
 void gz_ctx_destroy(gz_ctx* c) {
   if (!c) return;
+  for (gz_plan* pl : c->live_plans) pl->ctx = nullptr;  // orphaned: destroy only
   for (int k = 0; k < STAGE_SLOTS; ++k) {
     if (c->stage_ev[k]) {
       (void)hipEventSynchronize(c->stage_ev[k]);
@@ -409,18 +476,27 @@ void gz_ctx_destroy(gz_ctx* c) {
   (void)hipFree(c->d_jobs);
   (void)hipFree(c->d_map);
   (void)hipFree(c->train_ws);
+  (void)hipFree(c->plan_jobs);
+  (void)hipFree(c->plan_map);
   delete c;
 }
 
-gz_status gz_ctx_status(gz_ctx* c, gz_status* dev) {
+gz_status gz_ctx_status(gz_ctx* c, gz_stream_t stream, gz_status* dev) {
   if (!c || !dev) return GZ_EINVAL;
-  if (hipDeviceSynchronize() != hipSuccess) return GZ_EHIP;
+  hipStream_t st = (hipStream_t)stream;
+  // the word is read after the stream's work, on the stream, into pageable
+  // host memory (a synchronous copy) -- only this stream is waited for
   uint32_t err = 0;
-  if (hipMemcpy(&err, &c->ctrl->err, 4, hipMemcpyDeviceToHost) != hipSuccess) return GZ_EHIP;
+  if (hipStreamSynchronize(st) != hipSuccess ||
+      hipMemcpyAsync(&err, &c->ctrl->err, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return GZ_EHIP;
   *dev = (err & gzk::ERRF_CORRUPT) ? GZ_ECORRUPT : (err & gzk::ERRF_TIMEOUT) ? GZ_ETIMEOUT : GZ_OK;
   if (err) {
-    uint32_t z = 0;
-    if (hipMemcpy(&c->ctrl->err, &z, 4, hipMemcpyHostToDevice) != hipSuccess) return GZ_EHIP;
+    static const uint32_t z = 0;
+    if (hipMemcpyAsync(&c->ctrl->err, &z, 4, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return GZ_EHIP;
   }
   return GZ_OK;
 }
@@ -673,26 +749,21 @@ gz_status gz_batch(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t nreq,
                    const gz_params* p, gz_stream_t stream) {
   if (!c || op > GZ_OP_ACCUMULATE) return GZ_EINVAL;
   if (p && !tpb_ok(p->threads)) return GZ_EINVAL;
-  if (!h_reqs) return GZ_EINVAL;
-  bool any_f64 = false;
-  for (uint32_t j = 0; j < nreq; ++j) any_f64 = any_f64 || h_reqs[j].dtype == GZ_F64;
-  const uint32_t tpb = pick_tpb(c, op, any_f64 ? GZ_F64 : GZ_F32, 32, p && p->threads ? p : nullptr);
+  if (!h_reqs || nreq == 0) return GZ_EINVAL;
+  bool wide;
+  const uint32_t tpb = batch_tpb(c, op, h_reqs, nreq, p, wide);
+  if (!tpb_fits(c, wide, false, tpb)) return GZ_EUNSUPPORTED;
   std::vector<Job> jobs;
   std::vector<uint32_t> map;
   gz_status r = build_requests(c, op, h_reqs, nreq, tpb, jobs, map);
   if (r != GZ_OK) return r;
-  bool wide = false;
-  for (const Job& J : jobs) wide = wide || J.dtype == GZ_F64;
-  if (!tpb_fits(c, wide, false, tpb)) return GZ_EUNSUPPORTED;
   hipStream_t st = (hipStream_t)stream;
   r = stage_upload(c, jobs, map, st);
   if (r != GZ_OK) return r;
-  uint64_t g = (p && p->grid) ? p->grid
-                              : (uint64_t)c->cus * gzk::occupancy_blocks(gzk::OCC_BATCH + (uint32_t)op, wide, 5, tpb);
-  g = std::max<uint64_t>(1, std::min<uint64_t>(g, map.size() / 2));
+  const uint64_t total = map.size() / 2;
+  const uint32_t g = batch_grid(c, op, wide, tpb, total, p);
   return hip_status(gzk::launch_batch((uint32_t)op, c->d_jobs, c->d_map, uniform_jobs(jobs),
-                                      (uint32_t)(map.size() / 2),
-                                      c->ctl(), tpb, (uint32_t)g, wide, st));
+                                      (uint32_t)total, c->ctl(), tpb, g, wide, st));
 }
 
 gz_status gz_plan_create(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t nreq,
@@ -700,34 +771,41 @@ gz_status gz_plan_create(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t
   if (!c || !out || op > GZ_OP_ACCUMULATE) return GZ_EINVAL;
   *out = nullptr;
   if (p && !tpb_ok(p->threads)) return GZ_EINVAL;
-  if (!h_reqs) return GZ_EINVAL;
-  bool any_f64 = false;
-  for (uint32_t j = 0; j < nreq; ++j) any_f64 = any_f64 || h_reqs[j].dtype == GZ_F64;
-  const uint32_t tpb = pick_tpb(c, op, any_f64 ? GZ_F64 : GZ_F32, 32, p && p->threads ? p : nullptr);
+  if (!h_reqs || nreq == 0) return GZ_EINVAL;
+  bool wide;
+  const uint32_t tpb = batch_tpb(c, op, h_reqs, nreq, p, wide);
+  if (!tpb_fits(c, wide, false, tpb)) return GZ_EUNSUPPORTED;
   std::vector<Job> jobs;
   std::vector<uint32_t> map;
   gz_status r = build_requests(c, op, h_reqs, nreq, tpb, jobs, map);
   if (r != GZ_OK) return r;
+  // a range released by gz_plan_destroy may still be read by a launch in
+  // flight: the device finishes its work before the arena is written
+  if (hipDeviceSynchronize() != hipSuccess) return GZ_EHIP;
+  uint64_t jo = 0, mo = 0;
+  if (!c->plan_jobs_arena.take(jobs.size(), jo)) return GZ_ENOSPC;
+  if (!c->plan_map_arena.take(map.size(), mo)) {
+    c->plan_jobs_arena.give(jo);
+    return GZ_ENOSPC;
+  }
   gz_plan* pl = new (std::nothrow) gz_plan();
-  if (!pl) return GZ_ENOMEM;
+  if (!pl) {
+    c->plan_jobs_arena.give(jo);
+    c->plan_map_arena.give(mo);
+    return GZ_ENOMEM;
+  }
   pl->ctx = c;
   pl->op = op;
+  pl->jobs_off = jo;
+  pl->map_off = mo;
+  pl->d_jobs = c->plan_jobs + jo;
+  pl->d_map = c->plan_map + mo;
   pl->total = (uint32_t)(map.size() / 2);
   pl->njobs = uniform_jobs(jobs);
   pl->tpb = tpb;
-  for (const Job& J : jobs) pl->wide = pl->wide || J.dtype == GZ_F64;
-  if (!tpb_fits(c, pl->wide, false, tpb)) {
-    gz_plan_destroy(pl);
-    return GZ_EUNSUPPORTED;
-  }
-  uint64_t g = (p && p->grid) ? p->grid
-                              : (uint64_t)c->cus * gzk::occupancy_blocks(gzk::OCC_BATCH + (uint32_t)op, pl->wide, 5, tpb);
-  pl->grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(g, map.size() / 2));
-  if (hipMalloc((void**)&pl->d_jobs, jobs.size() * sizeof(Job)) != hipSuccess ||
-      hipMalloc((void**)&pl->d_map, map.size() * 4) != hipSuccess) {
-    gz_plan_destroy(pl);
-    return GZ_ENOMEM;
-  }
+  pl->wide = wide;
+  pl->grid = batch_grid(c, op, wide, tpb, pl->total, p);
+  c->live_plans.push_back(pl);
   if (hipMemcpy(pl->d_jobs, jobs.data(), jobs.size() * sizeof(Job), hipMemcpyHostToDevice) !=
           hipSuccess ||
       hipMemcpy(pl->d_map, map.data(), map.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
@@ -739,7 +817,7 @@ gz_status gz_plan_create(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t
 }
 
 gz_status gz_plan_launch(gz_plan* pl, gz_stream_t stream) {
-  if (!pl) return GZ_EINVAL;
+  if (!pl || !pl->ctx) return GZ_EINVAL;
   return hip_status(gzk::launch_batch(pl->op, pl->d_jobs, pl->d_map, pl->njobs, pl->total,
                                       pl->ctx->ctl(),
                                       pl->tpb, pl->grid, pl->wide, (hipStream_t)stream));
@@ -747,8 +825,12 @@ gz_status gz_plan_launch(gz_plan* pl, gz_stream_t stream) {
 
 void gz_plan_destroy(gz_plan* pl) {
   if (!pl) return;
-  (void)hipFree(pl->d_jobs);
-  (void)hipFree(pl->d_map);
+  if (gz_ctx* c = pl->ctx) {
+    c->plan_jobs_arena.give(pl->jobs_off);
+    c->plan_map_arena.give(pl->map_off);
+    c->live_plans.erase(std::remove(c->live_plans.begin(), c->live_plans.end(), pl),
+                        c->live_plans.end());
+  }
   delete pl;
 }
 
@@ -833,14 +915,14 @@ static void cache_store(const char* path, const std::string& key, uint32_t tpb, 
   fclose(f);
 }
 
-static gz_status time_op(gz_ctx* c, uint32_t op, void* x, void* s, uint64_t cap,
-                         unsigned long long* nb, uint64_t n, gz_dtype dt, uint32_t L,
-                         uint32_t tpb, uint32_t grid, hipStream_t st, hipEvent_t e0,
-                         hipEvent_t e1, float& ms) {
+static gz_status time_op(gz_ctx* c, uint32_t op, const void* x, void* y, void* s,
+                         uint64_t cap, unsigned long long* nb, uint64_t n, gz_dtype dt,
+                         uint32_t L, uint32_t tpb, uint32_t grid, hipStream_t st,
+                         hipEvent_t e0, hipEvent_t e1, float& ms) {
   gz_params p = {L, tpb, grid, 0, 0, 0};
   auto run = [&]() -> gz_status {
     return op == 0 ? gz_compress(c, x, n, dt, 1e-3, &p, s, cap, (uint64_t*)nb, st)
-                   : gz_decompress(c, s, cap, n, dt, &p, x, st);
+                   : gz_decompress(c, s, cap, n, dt, &p, y, st);
   };
   gz_status r = run();
   if (r != GZ_OK) return r;
@@ -854,23 +936,29 @@ static gz_status time_op(gz_ctx* c, uint32_t op, void* x, void* s, uint64_t cap,
   return GZ_OK;
 }
 
-gz_status gz_tune(gz_ctx* c, gz_dtype dt, uint32_t block_len, uint64_t n, const char* cache_path,
-                  gz_params* best) {
+static uint64_t round256(uint64_t a) { return (a + 255) & ~255ull; }
+
+gz_status gz_tune(gz_ctx* c, gz_dtype dt, uint32_t block_len, const void* d_sample, uint64_t n,
+                  void* d_work, uint64_t work_bytes, const char* cache_path, gz_params* best,
+                  gz_stream_t stream) {
   if (!c || (dt != GZ_F32 && dt != GZ_F64) || n == 0 || n > c->max_elems) return GZ_EINVAL;
   if (block_len != 0 && !valid_L(block_len)) return GZ_EINVAL;
+  if (!d_sample || !d_work) return GZ_EINVAL;
+  // the caller's work buffer: decoded values | stream (the largest bound of
+  // the three lengths) | size word
+  const uint64_t cap = bound_of(n, dt, 32);
+  const uint64_t dec_b = round256(n * esize(dt)), str_b = round256(cap);
+  if (work_bytes < dec_b + str_b + 8) return GZ_ENOSPC;
+  if (overlaps(d_sample, n * esize(dt), d_work, work_bytes)) return GZ_EINVAL;
+  uint8_t* w = (uint8_t*)d_work;
+  void* y = w;
+  void* s = w + dec_b;
+  unsigned long long* nb = (unsigned long long*)(w + dec_b + str_b);
   const uint32_t Ls[3] = {32, 64, 128};
-  const uint64_t cap = bound_of(n, dt, 32);  // the largest bound of the three
-  void *x = nullptr, *s = nullptr;
-  unsigned long long* nb = nullptr;
-  hipStream_t st = nullptr;
+  hipStream_t st = (hipStream_t)stream;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   gz_status r = GZ_OK;
-  if (hipMalloc(&x, n * esize(dt)) != hipSuccess || hipMalloc(&s, cap) != hipSuccess ||
-      hipMalloc((void**)&nb, 8) != hipSuccess ||
-      hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
-    r = GZ_ENOMEM;
-  if (r == GZ_OK) r = hip_status(gzk::launch_fill(x, n, dt, st));
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) r = GZ_EHIP;
   float best_total = 1e30f;
   uint32_t best_L = block_len ? block_len : 32;
   for (int li = 0; r == GZ_OK && li < 3; ++li) {
@@ -884,7 +972,7 @@ gz_status gz_tune(gz_ctx* c, gz_dtype dt, uint32_t block_len, uint64_t n, const 
       uint32_t tpb = 0, grid = 0;
       float ms = 0;
       if (cache_lookup(cache_path, keyb, tpb, grid) && tpb_fits(c, dt == GZ_F64, false, tpb)) {
-        r = time_op(c, op, x, s, cap, nb, n, dt, L, tpb, grid, st, e0, e1, ms);
+        r = time_op(c, op, d_sample, y, s, cap, nb, n, dt, L, tpb, grid, st, e0, e1, ms);
       } else {
         float bms = 1e30f;
         const uint32_t tpbs[4] = {128, 256, 512, 1024};
@@ -895,7 +983,8 @@ gz_status gz_tune(gz_ctx* c, gz_dtype dt, uint32_t block_len, uint64_t n, const 
                                      (uint32_t)(c->cus * occ * 2)};
           for (uint32_t gi = 0; r == GZ_OK && gi < 4; ++gi) {
             float t = 0;
-            r = time_op(c, op, x, s, cap, nb, n, dt, L, tpbs[ti], grids[gi], st, e0, e1, t);
+            r = time_op(c, op, d_sample, y, s, cap, nb, n, dt, L, tpbs[ti], grids[gi], st, e0,
+                        e1, t);
             if (r == GZ_OK && t < bms) {
               bms = t;
               tpb = tpbs[ti];
@@ -918,17 +1007,67 @@ gz_status gz_tune(gz_ctx* c, gz_dtype dt, uint32_t block_len, uint64_t n, const 
     }
   }
   if (r == GZ_OK && hipStreamSynchronize(st) != hipSuccess) r = GZ_EHIP;
+  if (r == GZ_OK && block_len == 0) c->best_L[dt] = best_L;  // for requests of length 0
   if (r == GZ_OK && best) {
     const Tuned& t = c->tuned[0][dt][log2_of(best_L) - 5];
     *best = gz_params{best_L, t.tpb, t.grid, 0, 0, 0};
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
-  if (st) (void)hipStreamDestroy(st);
-  (void)hipFree(x);
-  (void)hipFree(s);
-  (void)hipFree(nb);
   return r;
+}
+
+gz_status gz_tune_batch(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t nreq,
+                        const char* cache_path, gz_params* best, gz_stream_t stream) {
+  if (!c || !h_reqs || nreq == 0 || op > GZ_OP_FUSED) return GZ_EINVAL;
+  bool wide = false;
+  uint64_t elems = 0;
+  for (uint32_t j = 0; j < nreq; ++j) {
+    wide = wide || h_reqs[j].dtype == GZ_F64;
+    elems += h_reqs[j].n;
+  }
+  char keyb[160];
+  snprintf(keyb, sizeof keyb, "gfx950/cus%d/batch/op%u/wide%u/nreq%u/elems%llu", c->cus,
+           (unsigned)op, wide ? 1u : 0u, nreq, (unsigned long long)elems);
+  uint32_t tpb = 0, grid = 0;
+  gz_status r = GZ_OK;
+  if (!(cache_lookup(cache_path, keyb, tpb, grid) && tpb_fits(c, wide, false, tpb))) {
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) r = GZ_EHIP;
+    float bms = 1e30f;
+    const uint32_t tpbs[4] = {128, 256, 512, 1024};
+    for (uint32_t ti = 0; r == GZ_OK && ti < 4; ++ti) {
+      if (!tpb_fits(c, wide, false, tpbs[ti])) continue;
+      const int occ = gzk::occupancy_blocks(gzk::OCC_BATCH + (uint32_t)op, wide, 5, tpbs[ti]);
+      const uint32_t grids[4] = {(uint32_t)c->cus, 2u * c->cus, (uint32_t)(c->cus * occ),
+                                 (uint32_t)(c->cus * occ * 2)};
+      for (uint32_t gi = 0; r == GZ_OK && gi < 4; ++gi) {
+        const gz_params p = {0, tpbs[ti], grids[gi], 0, 0, 0};
+        r = gz_batch(c, op, h_reqs, nreq, &p, st);  // warm-up
+        if (r == GZ_OK && hipEventRecord(e0, st) != hipSuccess) r = GZ_EHIP;
+        for (int k = 0; k < 3 && r == GZ_OK; ++k) r = gz_batch(c, op, h_reqs, nreq, &p, st);
+        float ms = 0;
+        if (r == GZ_OK && (hipEventRecord(e1, st) != hipSuccess ||
+                           hipEventSynchronize(e1) != hipSuccess ||
+                           hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+          r = GZ_EHIP;
+        if (r == GZ_OK && ms < bms) {
+          bms = ms;
+          tpb = tpbs[ti];
+          grid = grids[gi];
+        }
+      }
+    }
+    if (r == GZ_OK && hipStreamSynchronize(st) != hipSuccess) r = GZ_EHIP;
+    if (r == GZ_OK) cache_store(cache_path, keyb, tpb, grid, bms / 3);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  }
+  if (r != GZ_OK) return r;
+  c->batch_tuned[op][wide ? 1 : 0] = Tuned{tpb, grid};
+  if (best) *best = gz_params{0, tpb, grid, 0, 0, 0};
+  return GZ_OK;
 }
 
 gz_status gz_selector_load(gz_ctx* c, const void* h_blob, uint64_t bytes) {

@@ -25,7 +25,6 @@ hipError_t launch_tiles(uint32_t op, const Job& J, const Ctl& C, uint32_t tpb, u
                         hipStream_t st);
 hipError_t launch_tile_trial(const Job& J, int8_t* feat, uint32_t* sizes, uint8_t* label,
                              hipStream_t st);
-hipError_t launch_fill(void* x, uint64_t n, uint32_t dtype, hipStream_t st);  // tuning input
 hipError_t launch_reset(const Ctl& C, hipStream_t st);
 // writes the sticky device status (a gz_status code) to *status, if given,
 // and clears it

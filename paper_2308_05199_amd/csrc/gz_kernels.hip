@@ -1516,7 +1516,7 @@ __device__ __forceinline__ void decompress_one(const Job& J, uint64_t s, const C
 
 // Decode-and-accumulate (fp32): acc[i] = fl32(decoded[i] + acc[i]), the
 // reduction that follows each receive in recursive-doubling Allreduce
-// (Sec. 3.3.2), without writing the decoded values to memory.  A whole
+// (Sec. 3.3.4), without writing the decoded values to memory.  A whole
 // strip's accumulator is read with coalesced loads issued before the decode,
 // so they are in flight while it runs.  A malformed stream leaves acc as it
 // was (and flags the context).
@@ -1908,21 +1908,6 @@ __global__ void k_quantize(const T* __restrict__ x, uint64_t n, Job J, int32_t* 
   }
 }
 
-// Smooth synthetic signal with hashed noise (autotuning input).
-template <typename T>
-__global__ void k_fill(T* __restrict__ x, uint64_t n) {
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
-       i += (uint64_t)gridDim.x * blockDim.x) {
-    const float u = (float)(i % 1048576) * (1.0f / 1048576.0f);
-    uint32_t h = (uint32_t)i * 2654435761u;
-    h ^= h >> 15;
-    h *= 2246822519u;
-    h ^= h >> 13;
-    const float noise = ((float)(h & 0xFFFFu) - 32768.0f) * (1.0e-3f / 32768.0f);
-    x[i] = (T)(sinf(6.2831853f * 7.0f * u) + 0.5f * sinf(6.2831853f * 31.0f * u) + noise);
-  }
-}
-
 // Clears the control block (after a device error) without a memset node.
 __global__ void k_reset(Ctl C) {
   if (threadIdx.x == 0) {
@@ -2085,13 +2070,6 @@ hipError_t launch_tile_trial(const Job& J, int8_t* feat, uint32_t* sizes, uint8_
   uint64_t blocks = (segs + 255) / 256;
   const uint32_t grid = (uint32_t)(blocks < 8192 ? (blocks ? blocks : 1) : 8192);
   hipLaunchKernelGGL(k_tile_trial, dim3(grid), dim3(256), 0, st, J, feat, sizes, label);
-  return hipGetLastError();
-}
-
-hipError_t launch_fill(void* x, uint64_t n, uint32_t dtype, hipStream_t st) {
-  const uint32_t grid = 4096;
-  if (dtype == 0) hipLaunchKernelGGL(k_fill<float>, dim3(grid), dim3(256), 0, st, (float*)x, n);
-  else hipLaunchKernelGGL(k_fill<double>, dim3(grid), dim3(256), 0, st, (double*)x, n);
   return hipGetLastError();
 }
 

@@ -44,7 +44,7 @@ _pp = ctypes.POINTER(gz_params)
 _SIGS = {
     "gz_ctx_create": ([ctypes.POINTER(_vp), _i32, _u64, _u32], _i32),
     "gz_ctx_destroy": ([_vp], None),
-    "gz_ctx_status": ([_vp, ctypes.POINTER(_i32)], _i32),
+    "gz_ctx_status": ([_vp, _vp, ctypes.POINTER(_i32)], _i32),
     "gz_ctx_reset": ([_vp, _vp], _i32),
     "gz_compress_bound": ([_u64, _i32, _u32], _u64),
     "gz_quantize": ([_vp, _vp, _u64, _i32, _dbl, _vp, _vp, _vp], _i32),
@@ -63,7 +63,9 @@ _SIGS = {
     "gz_graph_create": ([ctypes.POINTER(_vp), _u32, ctypes.POINTER(_vp)], _i32),
     "gz_graph_launch": ([_vp, _vp], _i32),
     "gz_graph_destroy": ([_vp], None),
-    "gz_tune": ([_vp, _i32, _u32, _u64, ctypes.c_char_p, _pp], _i32),
+    "gz_tune": ([_vp, _i32, _u32, _vp, _u64, _vp, _u64, ctypes.c_char_p, _pp, _vp], _i32),
+    "gz_tune_batch": ([_vp, _i32, ctypes.POINTER(gz_request), _u32, ctypes.c_char_p, _pp, _vp],
+                      _i32),
     "gz_selector_load": ([_vp, _vp, _u64], _i32),
     "gz_tile_trial": ([_vp, _vp, _u64, _u32, _dbl, _vp, _vp, _vp, _vp], _i32),
     "gz_mlp_grad": ([_vp, _vp, _vp, _vp, _u64, _vp, _vp, _vp], _i32),
@@ -78,11 +80,12 @@ for _name, (_args, _res) in _SIGS.items():
     globals()[_name] = _f
 
 EXPORTED = tuple(_SIGS)
+_STATUS_TEXT = {k: gz_status_str(k).decode() for k in range(8)}
 
 
 class GzError(RuntimeError):
     def __init__(self, status, what):
-        msg = gz_status_str(status).decode()
+        msg = _STATUS_TEXT.get(status, "unknown status")
         super().__init__(f"{what}: {msg} (status {status})")
         self.status = status
 
@@ -99,6 +102,32 @@ def _stream(stream=None):
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else ctypes.c_void_p(0)
+
+
+_F = (torch.float32, torch.float64)
+
+
+def _need(t, what, name, dtypes=None, numel=None):
+    """Raises GzError (nothing is enqueued) unless t is a contiguous tensor on
+    a GPU device, of one of `dtypes`, with at least `numel` elements: the C
+    ABI takes raw device pointers, so a host tensor, a strided view or a
+    narrower dtype would make the kernels read or write the wrong memory."""
+    if not isinstance(t, torch.Tensor):
+        raise GzError(GZ_EINVAL, f"{what}: {name} must be a torch tensor")
+    if not t.is_contiguous():
+        raise GzError(GZ_EINVAL, f"{what}: {name} must be contiguous")
+    if dtypes is not None and t.dtype not in dtypes:
+        raise GzError(GZ_EINVAL, f"{what}: {name} must be {'/'.join(str(d) for d in dtypes)}, "
+                                 f"not {t.dtype}")
+    if numel is not None and t.numel() < numel:
+        raise GzError(GZ_EINVAL, f"{what}: {name} holds {t.numel()} elements, needs {numel}")
+    if not _on_gpu(t):
+        raise GzError(GZ_EINVAL, f"{what}: {name} must be on a GPU device, not {t.device}")
+    return t
+
+
+def _on_gpu(t):
+    return t.is_cuda
 
 
 def _dt(t):
@@ -122,6 +151,12 @@ def compress_noalloc(x, eb, out, out_bytes, status, block_len=32, threads=0, gri
     """gz_compress without a context, for callers that cannot allocate:
     out (uint8, at least bound() bytes), out_bytes (int64[1]) and status
     (int32[1]) are caller-owned device tensors; nothing is allocated."""
+    what = "gz_compress_noalloc"
+    _need(x, what, "x", _F)
+    _need(out, what, "out", (torch.uint8,), bound(x.numel(), _dt(x), block_len))
+    _need(out_bytes, what, "out_bytes", (torch.int64,), 1)
+    if status is not None:
+        _need(status, what, "status", (torch.int32,), 1)
     p = _params(block_len, threads, grid, mode, select, nx)
     check(gz_compress_noalloc(_ptr(x), x.numel(), _dt(x), eb, ctypes.byref(p), _ptr(out),
                               out.numel(), _ptr(out_bytes), _ptr(status), _stream(stream)),
@@ -150,15 +185,41 @@ class Context:
         except Exception:
             pass
 
-    def device_status(self):
+    def device_status(self, stream=None):
+        """Waits for `stream` (default: the current one) and returns and
+        clears the sticky device status."""
         st = _i32(0)
-        check(gz_ctx_status(self.h, ctypes.byref(st)), "gz_ctx_status")
+        check(gz_ctx_status(self.h, _stream(stream), ctypes.byref(st)), "gz_ctx_status")
         return st.value
 
-    def reset(self, stream=None):
-        check(gz_ctx_reset(self.h, _stream(stream)), "gz_ctx_reset")
+    def tune(self, sample, block_len=0, cache_path=None, stream=None):
+        """Autotunes launch shapes (and, with block_len 0, the block length of
+        requests that give 0) for single calls of sample's dtype and size,
+        timed on the sample itself.  Returns the best params."""
+        what = "gz_tune"
+        _need(sample, what, "sample", _F)
+        n = sample.numel()
+        es = sample.element_size()
+        r256 = lambda a: (a + 255) // 256 * 256
+        work = torch.empty(r256(n * es) + r256(bound(n, _dt(sample), 32)) + 8,
+                           dtype=torch.uint8, device=sample.device)
+        best = gz_params()
+        cp = cache_path.encode() if isinstance(cache_path, str) else cache_path
+        check(gz_tune(self.h, _dt(sample), block_len, _ptr(sample), n, _ptr(work),
+                      work.numel(), cp, ctypes.byref(best), _stream(stream)), what)
+        return best
+
+    def tune_batch(self, op, reqs, cache_path=None, stream=None):
+        """Autotunes (threads, grid) of this batch's op and element-type mix;
+        runs the batch in place.  Returns the best params."""
+        best = gz_params()
+        cp = cache_path.encode() if isinstance(cache_path, str) else cache_path
+        check(gz_tune_batch(self.h, op, reqs, len(reqs), cp, ctypes.byref(best),
+                            _stream(stream)), "gz_tune_batch")
+        return best
 
     def quantize(self, x, eb, stream=None):
+        _need(x, "gz_quantize", "x", _F)
         q = torch.empty(x.numel(), dtype=torch.int32, device=x.device)
         f = torch.empty(x.numel(), dtype=torch.uint8, device=x.device)
         check(gz_quantize(self.h, _ptr(x), x.numel(), _dt(x), eb, _ptr(q), _ptr(f),
@@ -167,12 +228,16 @@ class Context:
 
     def compress(self, x, eb, block_len=32, threads=0, grid=0, out=None, out_bytes=None,
                  stream=None):
+        what = "gz_compress"
+        _need(x, what, "x", _F)
         n = x.numel()
         cap = bound(n, _dt(x), block_len)
         if out is None:
             out = torch.empty(cap, dtype=torch.uint8, device=x.device)
         if out_bytes is None:
             out_bytes = torch.zeros(1, dtype=torch.int64, device=x.device)
+        _need(out, what, "out", (torch.uint8,))
+        _need(out_bytes, what, "out_bytes", (torch.int64,), 1)
         p = _params(block_len, threads, grid)
         check(gz_compress(self.h, _ptr(x), n, _dt(x), eb, ctypes.byref(p), _ptr(out),
                           out.numel(), _ptr(out_bytes), _stream(stream)), "gz_compress")
@@ -180,9 +245,14 @@ class Context:
 
     def decompress(self, stream_buf, n, dtype=torch.float32, block_len=32, in_bytes=None,
                    threads=0, grid=0, out=None, stream=None):
+        what = "gz_decompress"
+        _need(stream_buf, what, "stream_buf", (torch.uint8,))
         if out is None:
             out = torch.empty(n, dtype=dtype, device=stream_buf.device)
+        _need(out, what, "out", _F, n)
         ib = stream_buf.numel() if in_bytes is None else in_bytes
+        if ib > stream_buf.numel():
+            raise GzError(GZ_EINVAL, f"{what}: in_bytes {ib} exceeds the buffer")
         p = _params(block_len, threads, grid)
         check(gz_decompress(self.h, _ptr(stream_buf), ib, n, _dt(out), ctypes.byref(p),
                             _ptr(out), _stream(stream)), "gz_decompress")
@@ -190,13 +260,20 @@ class Context:
 
     def fused_reduce_step(self, stream_in, local, eb, block_len=32, in_bytes=None, threads=0,
                           grid=0, out=None, out_bytes=None, stream=None):
+        what = "gz_fused_reduce_step"
+        _need(stream_in, what, "stream_in", (torch.uint8,))
+        _need(local, what, "local", (torch.float32,))
         n = local.numel()
         cap = bound(n, GZ_F32, block_len)
         if out is None:
             out = torch.empty(cap, dtype=torch.uint8, device=local.device)
         if out_bytes is None:
             out_bytes = torch.zeros(1, dtype=torch.int64, device=local.device)
+        _need(out, what, "out", (torch.uint8,))
+        _need(out_bytes, what, "out_bytes", (torch.int64,), 1)
         ib = stream_in.numel() if in_bytes is None else in_bytes
+        if ib > stream_in.numel():
+            raise GzError(GZ_EINVAL, f"{what}: in_bytes {ib} exceeds the buffer")
         p = _params(block_len, threads, grid)
         check(gz_fused_reduce_step(self.h, _ptr(stream_in), ib, _ptr(local), n, eb,
                                    ctypes.byref(p), _ptr(out), out.numel(), _ptr(out_bytes),
@@ -206,9 +283,12 @@ class Context:
     def decompress_add(self, stream_in, acc, block_len=32, in_bytes=None, threads=0, grid=0,
                        stream=None):
         """acc (fp32, on the device) += decoded stream, in place."""
-        if acc.dtype != torch.float32 or not acc.is_contiguous() or not acc.is_cuda:
-            raise GzError(GZ_EINVAL, "decompress_add: acc must be a contiguous fp32 device tensor")
+        what = "gz_decompress_add"
+        _need(stream_in, what, "stream_in", (torch.uint8,))
+        _need(acc, what, "acc", (torch.float32,))
         ib = stream_in.numel() if in_bytes is None else in_bytes
+        if ib > stream_in.numel():
+            raise GzError(GZ_EINVAL, f"{what}: in_bytes {ib} exceeds the buffer")
         p = _params(block_len, threads, grid)
         check(gz_decompress_add(self.h, _ptr(stream_in), ib, acc.numel(), ctypes.byref(p),
                                 _ptr(acc), _stream(stream)), "gz_decompress_add")
@@ -216,12 +296,15 @@ class Context:
 
     def scatter_compress(self, root, counts, displs, eb, block_len=32, threads=0, grid=0,
                          out=None, stream=None):
+        what = "gz_scatter_compress"
         counts = np.ascontiguousarray(counts, dtype=np.uint64)
         displs = np.ascontiguousarray(displs, dtype=np.uint64)
+        _need(root, what, "root", _F, int((displs + counts).max()) if len(counts) else 0)
         dt = _dt(root)
         cap = sum(bound(int(c), dt, block_len) for c in counts)
         if out is None:
             out = torch.empty(cap, dtype=torch.uint8, device=root.device)
+        _need(out, what, "out", (torch.uint8,))
         cb = torch.zeros(len(counts), dtype=torch.int64, device=root.device)
         co = torch.zeros(len(counts), dtype=torch.int64, device=root.device)
         p = _params(block_len, threads, grid)
@@ -236,10 +319,16 @@ class Context:
                            stream=None):
         counts = np.ascontiguousarray(counts, dtype=np.uint64)
         displs = np.ascontiguousarray(displs, dtype=np.uint64)
+        what = "gz_scatter_decompress"
         total = int((displs + counts).max()) if len(counts) else 0
+        _need(packed, what, "packed", (torch.uint8,))
+        _need(chunk_offsets, what, "chunk_offsets", (torch.int64,), len(counts))
         if out is None:
             out = torch.empty(total, dtype=dtype, device=packed.device)
+        _need(out, what, "out", _F, total)
         pb = packed.numel() if packed_bytes is None else packed_bytes
+        if pb > packed.numel():
+            raise GzError(GZ_EINVAL, f"{what}: packed_bytes {pb} exceeds the buffer")
         p = _params(block_len, threads, grid)
         check(gz_scatter_decompress(self.h, _ptr(packed), pb, _ptr(chunk_offsets), _dt(out),
                                     counts.ctypes.data_as(_vp), displs.ctypes.data_as(_vp),
@@ -254,6 +343,25 @@ class Context:
         tensors alive while it is in use)."""
         arr = (gz_request * len(items))()
         for i, it in enumerate(items):
+            what = f"request {i}"
+            n = int(it["n"])
+            es = 4 if it["dtype"] == GZ_F32 else 8
+            for key in ("in", "out"):
+                t = it.get(key)
+                if t is None:
+                    continue
+                _need(t, what, key, (torch.uint8,) + _F)
+                if t.dtype == torch.uint8:   # a stream: its stated size must fit
+                    need = it.get("in_bytes", 0) if key == "in" else it.get("out_cap", 0)
+                    if t.numel() < need:
+                        raise GzError(GZ_EINVAL, f"{what}: {key} holds {t.numel()} bytes, "
+                                                 f"needs {need}")
+                elif t.numel() * t.element_size() < n * es:
+                    raise GzError(GZ_EINVAL, f"{what}: {key} holds fewer than {n} elements")
+            if it.get("local") is not None:
+                _need(it["local"], what, "local", (torch.float32,), n)
+            if it.get("out_bytes") is not None:
+                _need(it["out_bytes"], what, "out_bytes", (torch.int64,), 1)
             r = arr[i]
             r.in_ = it["in"].data_ptr() if it.get("in") is not None else 0
             r.local = it["local"].data_ptr() if it.get("local") is not None else 0
@@ -264,7 +372,7 @@ class Context:
             r.out_cap = it.get("out_cap", 0)
             r.eb = it.get("eb", 0.0)
             r.dtype = it["dtype"]
-            r.block_len = it.get("block_len", 32)
+            r.block_len = it.get("block_len", 32)   # 0: the tuned length
         return arr
 
     def batch(self, op, reqs, threads=0, grid=0, stream=None):

@@ -128,3 +128,34 @@ def pack_blob(W1q, b1q, shift, W2q, b2q):
 def load(ctx, blob):
     buf = ctypes.create_string_buffer(bytes(blob), len(blob))
     gzccl.check(gzccl.gz_selector_load(ctx.h, buf, len(blob)), "gz_selector_load")
+
+
+def fit(ctx, fields, steps=1500, seed=0, log=None):
+    """The whole training pipeline on the GPU: exhaustive-trial labels of
+    every tile of `fields` ((tensor, nx, eb) on the device), Adam on the
+    fp32 shadow network, int8 export calibrated on up to 50k labelled
+    tiles, and loading into ctx.  Returns the blob and the label counts
+    (NONE, L1D, L2D, skipped)."""
+    feats, labels = [], []
+    for x, nx, eb in fields:
+        f, _, lab = trial(ctx, x, nx, eb)
+        feats.append(f)
+        labels.append(lab)
+    feat = torch.cat(feats)
+    lab = torch.cat(labels)
+    counts = [int((lab == k).sum()) for k in range(NOUT)] + [int((lab >= NOUT).sum())]
+    w = train(ctx, feat, lab, steps=steps, seed=seed, log=log)
+    keep = (lab < NOUT).nonzero().view(-1)
+    calib = feat[keep[:: max(1, keep.numel() // 50000)]].cpu().numpy()
+    blob = export_int8(w.cpu().numpy(), calib)
+    load(ctx, blob)
+    return blob, counts
+
+
+def tile_compress(ctx, x, nx, eb, select, out, out_bytes, threads=0, stream=None):
+    """Tile-mode compression of x (device fp32, rows of nx) with selector
+    `select` (0 MLP, 1 exhaustive trial, 2 always L1D) into out."""
+    p = gzccl.gz_params(64, threads, 0, 1, select, nx)
+    gzccl.check(gzccl.gz_compress(ctx.h, gzccl._ptr(x), x.numel(), gzccl.GZ_F32, eb,
+                                  ctypes.byref(p), gzccl._ptr(out), out.numel(),
+                                  gzccl._ptr(out_bytes), gzccl._stream(stream)), "gz_compress")

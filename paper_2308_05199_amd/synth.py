@@ -172,3 +172,81 @@ def selector_fields(seed=0, grf_shape=(64, 256, 256), n_images=2, image_hw=(1024
         rng_ = float(x.max()) - float(x.min())
         res.append((x.astype(np.float32), nx, 1e-4 * (rng_ if rng_ > 0 else 1.0)))
     return res
+
+
+# ---- the same recipes drawn on the device (torch), for workloads too large
+# to generate on the host.  Seeded with torch's device generator.
+
+def device_grf(shape, seed, slope=-3.0):
+    """The grf() recipe (P(k) ~ k^slope, k = 0 removed, mean 0, std 1) on the
+    device with torch.fft; flat float32 tensor."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    spec = torch.fft.rfftn(torch.randn(shape, device="cuda", generator=g))
+    k2 = torch.zeros(spec.shape, device="cuda")
+    for ax, n in enumerate(shape):
+        fr = torch.fft.rfftfreq(n, device="cuda") if ax == len(shape) - 1 else \
+            torch.fft.fftfreq(n, device="cuda")
+        sh = [1] * len(shape)
+        sh[ax] = fr.numel()
+        k2 = k2 + fr.view(sh) ** 2
+    k2[(0,) * len(shape)] = 1.0
+    amp = k2 ** (slope / 4.0)
+    amp[(0,) * len(shape)] = 0.0
+    f = torch.fft.irfftn(spec * amp, s=shape)
+    return ((f - f.mean()) / f.std()).float().reshape(-1)
+
+
+def device_frames(nframes, h=2048, w=2048, seed=0):
+    """The frames() recipe (gradient background + Poisson(50) + 1e-4 point
+    sources with a sigma-1 Gaussian PSF) on the device; flat float32."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    yy = torch.arange(h, device="cuda", dtype=torch.float32).view(h, 1)
+    xx = torch.arange(w, device="cuda", dtype=torch.float32).view(1, w)
+    out = torch.empty((nframes, h, w), device="cuda")
+    r = torch.arange(-3, 4, device="cuda", dtype=torch.float32)
+    psf = torch.exp(-(r.view(-1, 1) ** 2 + r.view(1, -1) ** 2) / 2)
+    for f in range(nframes):
+        a = 100 + 100 * torch.rand(1, device="cuda", generator=g)
+        b, c = (torch.rand(2, device="cuda", generator=g) - 0.5) * 0.1
+        img = a + b * xx + c * yy
+        img = img + torch.poisson(torch.full((h, w), 50.0, device="cuda"), generator=g)
+        ns = int(1e-4 * h * w)
+        ys = torch.randint(3, h - 3, (ns,), device="cuda", generator=g)
+        xs = torch.randint(3, w - 3, (ns,), device="cuda", generator=g)
+        pk = 1e3 + 9e3 * torch.rand(ns, device="cuda", generator=g)
+        src = torch.zeros((h, w), device="cuda")
+        src.index_put_((ys, xs), pk, accumulate=True)
+        img = img + torch.nn.functional.conv2d(src.view(1, 1, h, w), psf.view(1, 1, 7, 7),
+                                               padding=3).view(h, w)
+        out[f] = img
+    return out.view(-1)
+
+
+def device_selector_fields(seed=0, n_grf=10, grf_shape=(256, 256, 256), n_images=40,
+                           image_hw=(2048, 2048), sparse_n=201 << 20):
+    """The selector workload on the device, as (tensor, nx, eb) with eb =
+    1e-4 x the field's range: n_grf smooth 3D GRFs viewed as rows of their
+    last axis, n_images noisy frames, and a 50%-zero sparse array as 8-wide
+    rows.  The defaults give 546 M elements (over 2^29); the fields of
+    different seeds are disjoint draws."""
+    import torch
+    fields = [(device_grf(grf_shape, seed * 1000 + 100 + k), grf_shape[-1])
+              for k in range(n_grf)]
+    if n_images:
+        imgs = device_frames(n_images, image_hw[0], image_hw[1],
+                             seed=seed * 1000 + 3).view(n_images, -1)
+        fields += [(imgs[k], image_hw[1]) for k in range(n_images)]
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed * 1000 + 5)
+    sp = torch.randn(sparse_n, device="cuda", generator=g) * \
+        (torch.rand(sparse_n, device="cuda", generator=g) < 0.5)
+    fields.append((sp, 8))
+    out = []
+    for x, nx in fields:
+        rng_ = float(x.max() - x.min())
+        out.append((x, nx, 1e-4 * (rng_ if rng_ > 0 else 1.0)))
+    return out

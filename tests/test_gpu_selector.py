@@ -1,5 +1,6 @@
 """GPU parity of the tile mode (8x8 tiles, NONE/L1D/L2D), the tile-trial
 kernel and the selector's training gradients against the CPU oracle."""
+import ctypes
 import sys
 
 import numpy as np
@@ -153,27 +154,6 @@ def test_adam_step_matches_formula(gz, ctx):
     assert np.allclose(W.cpu().numpy(), want, rtol=1e-5, atol=1e-6)
 
 
-def _device_grf(torch, shape, seed, slope=-3.0):
-    """The GRF recipe (P(k) ~ k^-3, k = 0 removed, mean 0, std 1) on the
-    device with torch.fft, so that the 512M-element workload needs no host
-    generation."""
-    g = torch.Generator(device="cuda")
-    g.manual_seed(seed)
-    spec = torch.fft.rfftn(torch.randn(shape, device="cuda", generator=g))
-    k2 = torch.zeros(spec.shape, device="cuda")
-    for ax, n in enumerate(shape):
-        fr = torch.fft.rfftfreq(n, device="cuda") if ax == len(shape) - 1 else \
-            torch.fft.fftfreq(n, device="cuda")
-        sh = [1] * len(shape)
-        sh[ax] = fr.numel()
-        k2 = k2 + fr.view(sh) ** 2
-    k2[0, 0, 0] = 1.0
-    amp = k2 ** (slope / 4.0)
-    amp[0, 0, 0] = 0.0
-    f = torch.fft.irfftn(spec * amp, s=shape)
-    return ((f - f.mean()) / f.std()).float().reshape(-1)
-
-
 def test_config4_full_size_sampled(gz, oracle):
     """512M fp32 elements of mixed fields (10 GRFs of 256^3 as 256-wide rows,
     40 noisy 2048^2 images, a 50%-zero sparse array as 8-wide rows) in tile
@@ -183,23 +163,12 @@ def test_config4_full_size_sampled(gz, oracle):
     bytes, and every element is within eb."""
     import ctypes
     import torch
-    sys.path.insert(0, __import__("os").path.dirname(__import__("os").path.dirname(
-        __import__("os").path.abspath(__file__))))
-    from bench import device_frames
-    from paper_2308_05199_amd import selector
+    from paper_2308_05199_amd import selector, synth
     say("config 4 full size")
     ctx = gz.Context(0, max_elems=1 << 28, max_requests=64)
     blob = random_blob(11)
     selector.load(ctx, blob)
-    fields = [(_device_grf(torch, (256, 256, 256), 100 + k), 256) for k in range(10)]
-    imgs = device_frames(torch, 40, seed=3).view(40, -1)
-    fields += [(imgs[k], 2048) for k in range(40)]
-    g = torch.Generator(device="cuda")
-    g.manual_seed(5)
-    ns = 201 * (1 << 20)  # brings the total to over 2^29
-    sp = torch.randn(ns, device="cuda", generator=g) * (torch.rand(ns, device="cuda",
-                                                                   generator=g) < 0.5)
-    fields.append((sp, 8))
+    fields = [(x, nx) for x, nx, _ in synth.device_selector_fields(0)]
     total = sum(f.numel() for f, _ in fields)
     assert total >= 512 * (1 << 20)
     say("fields ready", total)
@@ -235,5 +204,60 @@ def test_config4_full_size_sampled(gz, oracle):
             assert heads[lo // 64:hi // 64].tobytes() == s[whoff:whoff + xw.size // 64].tobytes()
             checked += 1
     say("windows checked", checked)
+    assert ctx.device_status() == 0
+    ctx.close()
+
+
+def test_trained_selector_against_exhaustive_trial(gz, oracle):
+    """The learned part end to end: the network is trained on the GPU (the
+    library's trial, gradient and Adam kernels) on labels from fields drawn
+    with seeds disjoint from the test set's, exported to int8 and loaded.
+    On the config-4 fields (546 M elements) its compression ratio is within
+    3% of exhaustive trial and above both the method without the network
+    (always-L1D tiles) and plain 1D blocks; its streams decode within eb, and
+    sampled windows equal the oracle's with the trained weights."""
+    import torch
+    from paper_2308_05199_amd import selector
+    say("trained selector")
+    ctx = gz.Context(0, max_elems=1 << 28, max_requests=64)
+    train = synth.device_selector_fields(1, n_grf=2, n_images=8, sparse_n=1 << 24)
+    blob, counts = selector.fit(ctx, train, steps=1500)
+    say("labels NONE/L1D/L2D/skipped", counts)
+    del train
+    test = synth.device_selector_fields(0)
+    raw = 0
+    size = {"mlp": 0, "exhaustive": 0, "l1d_tiles": 0, "blocks_1d": 0}
+    rng = np.random.default_rng(2)
+    for idx, (x, nx, eb) in enumerate(test):
+        n = x.numel()
+        raw += 4 * n
+        out = torch.empty(gz.bound(n, gz.GZ_F32, 32), dtype=torch.uint8, device="cuda")
+        nb = torch.zeros(1, dtype=torch.int64, device="cuda")
+        for key, sel in (("exhaustive", 1), ("l1d_tiles", 2), ("mlp", 0)):
+            selector.tile_compress(ctx, x, nx, eb, sel, out, nb)
+            torch.cuda.synchronize()
+            size[key] += int(nb.item())
+        if idx % 10 == 0 or idx == len(test) - 1:    # the MLP stream: decode and windows
+            y = torch.empty(n, device="cuda")
+            p = tile_params(gz, nx, 0)
+            gz.check(gz.gz_decompress(ctx.h, gz._ptr(out), int(nb.item()), n, gz.GZ_F32,
+                                      ctypes.byref(p), gz._ptr(y), gz._stream(None)), "untile")
+            torch.cuda.synchronize()
+            assert float((y.double() - x.double()).abs().max()) <= eb, idx
+            rows = n // nx
+            r0 = int(rng.integers(0, rows // 8 - 8)) * 8
+            xw = x[r0 * nx:(r0 + 64) * nx].cpu().numpy()
+            s = oracle.compress(xw, eb, block_len=64, mode=1, nx=nx, select=0, blob=blob)
+            assert y[r0 * nx:(r0 + 64) * nx].cpu().numpy().tobytes() == \
+                oracle.decompress(s).tobytes(), idx
+        ctx.compress(x, eb, block_len=32, out=out, out_bytes=nb)
+        torch.cuda.synchronize()
+        size["blocks_1d"] += int(nb.item())
+    ratio = {k: raw / v for k, v in size.items()}
+    say("ratios", {k: round(v, 4) for k, v in ratio.items()},
+        "mlp/exhaustive", round(ratio["mlp"] / ratio["exhaustive"], 4))
+    assert ratio["mlp"] >= 0.97 * ratio["exhaustive"]
+    assert ratio["mlp"] > ratio["l1d_tiles"]
+    assert ratio["mlp"] > ratio["blocks_1d"]
     assert ctx.device_status() == 0
     ctx.close()

@@ -459,3 +459,36 @@ def test_quantize_exhaustive_fp32(oracle):
                 good = ok & (np.abs(x.astype(np.float64) - xh.astype(np.float64)) <= eb)
             assert np.array_equal(fail, ~good)
             assert np.array_equal(q[good], qr[good])
+
+
+@pytest.mark.parametrize("L", [32, 64, 128])
+def test_all_core_variants_write_the_same_bytes(oracle, L):
+    """The OpenMP variants (superblocks at once, serial offset scan) give the
+    scalar oracle's bytes and values: fp32 and fp64, a ragged tail, RAW and
+    ZERO blocks, tile mode with every selector, and the fused step."""
+    from paper_2308_05199_amd import synth
+    rng = np.random.default_rng(L)
+    n = 5 * 4096 + 1234
+    x = synth.sinusoids(n, seed=L).astype(np.float64)
+    x[100:4200] = 0.0
+    x[7000] = np.nan
+    x[9000:9100] = 1e12
+    for dt in (np.float32, np.float64):
+        xs = x.astype(dt)
+        s = oracle.compress(xs, 1e-4, block_len=L)
+        assert oracle.compress(xs, 1e-4, block_len=L, mt=True).tobytes() == s.tobytes()
+        assert oracle.decompress(s, mt=True).tobytes() == oracle.decompress(s).tobytes()
+    loc = rng.standard_normal(n).astype(np.float32)
+    s = oracle.compress(x.astype(np.float32), 1e-4, block_len=L)
+    assert (oracle.fused_step(s, loc, 1e-4, block_len=L, mt=True).tobytes() ==
+            oracle.fused_step(s, loc, 1e-4, block_len=L).tobytes())
+    if L == 64:
+        t = synth.sinusoids(64 * 8 * 40, seed=3)
+        blob = bytes(np.random.default_rng(0).integers(-3, 4, 756).astype(np.int8))
+        blob = b"GZM1" + (4).to_bytes(4, "little") + blob[8:520] + bytes(4 * 32) + \
+            blob[552:648] + bytes(12)
+        for sel in (0, 1, 2):
+            a = oracle.compress(t, 1e-4, block_len=64, mode=1, nx=64, select=sel, blob=blob)
+            b = oracle.compress(t, 1e-4, block_len=64, mode=1, nx=64, select=sel, blob=blob,
+                                mt=True)
+            assert a.tobytes() == b.tobytes()
