@@ -430,8 +430,7 @@ gz_status gz_ctx_create(gz_ctx** out, int device, uint64_t max_elems, uint32_t m
   ok = ok && hipMalloc((void**)&c->blob, 1024) == hipSuccess;
   ok = ok && hipMalloc((void**)&c->d_jobs, (size_t)max_requests * sizeof(Job)) == hipSuccess;
   ok = ok && hipMalloc((void**)&c->d_map, c->max_strips * 8) == hipSuccess;
-  ok = ok && hipMalloc((void**)&c->train_ws,
-                       (size_t)gzs::MLP_MAX_BATCH * gzs::MLP_ROW * sizeof(float)) == hipSuccess;
+  ok = ok && hipMalloc((void**)&c->train_ws, gzs::mlp_workspace_bytes()) == hipSuccess;
   // live plans may hold up to 16 batches' worth of descriptors and maps
   c->plan_jobs_arena.cap = 16ull * max_requests + 64;
   c->plan_map_arena.cap = 16ull * 2 * c->max_strips + 1024;

@@ -4,8 +4,8 @@
 // tile's predictor (NONE, L1D, L2D).  It is trained as an fp32 "shadow"
 // network with softmax cross-entropy on labels from exhaustive trial, then
 // exported to int8.  Gradients are made deterministic: a per-sample kernel
-// writes each sample's backward terms, and a reduction kernel sums them in
-// sample order in fp64, one thread per parameter.
+// writes each sample's backward terms, and two reduction kernels sum them in
+// a fixed order in fp64 (per group of 64 samples, then over the groups).
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -71,42 +71,69 @@ __global__ __launch_bounds__(256) void k_mlp_fwdbwd(const float* __restrict__ w,
   out[2 * NH + NOUT] = logf(S) + m - z2[lab];
 }
 
-// One block; thread p sums parameter p's gradient over the samples in order.
-__global__ __launch_bounds__(1024) void k_mlp_reduce(const int8_t* __restrict__ feat,
+// Gradient sums in a fixed order, in two levels: block g sums every
+// parameter over its GROUP consecutive samples (staged in LDS) into
+// part[g][p]; then one thread per parameter adds the groups in group order.
+// Slot NPARAM of a group holds the loss sum, slot NPARAM + 1 the number of
+// labelled samples.
+constexpr int GROUP = 64;
+constexpr int PSTRIDE = NPARAM + 2;
+
+__global__ __launch_bounds__(704) void k_mlp_partial(const int8_t* __restrict__ feat,
                                                     const uint8_t* __restrict__ label,
                                                     uint32_t nsamp, const float* __restrict__ ws,
-                                                    float* __restrict__ grad,
-                                                    float* __restrict__ loss) {
-  __shared__ uint32_t cnt_part[1024];
-  uint32_t cnt = 0;
-  for (uint32_t s = threadIdx.x; s < nsamp; s += blockDim.x) cnt += label[s] < NOUT ? 1u : 0u;
-  cnt_part[threadIdx.x] = cnt;
+                                                    double* __restrict__ part) {
+  __shared__ float srow[GROUP * ROW];
+  __shared__ float sfeat[GROUP * NIN];
+  __shared__ uint32_t slab[GROUP];
+  const uint32_t s0 = blockIdx.x * GROUP;
+  const uint32_t m = min((uint32_t)GROUP, nsamp - s0);
+  for (uint32_t k = threadIdx.x; k < m * ROW; k += blockDim.x)
+    srow[k] = ws[(uint64_t)s0 * ROW + k];
+  for (uint32_t k = threadIdx.x; k < m * NIN; k += blockDim.x)
+    sfeat[k] = (float)feat[(uint64_t)s0 * NIN + k];
+  for (uint32_t k = threadIdx.x; k < m; k += blockDim.x) slab[k] = label[s0 + k];
   __syncthreads();
-  for (uint32_t st = blockDim.x / 2; st > 0; st >>= 1) {
-    if (threadIdx.x < st) cnt_part[threadIdx.x] += cnt_part[threadIdx.x + st];
-    __syncthreads();
-  }
-  const double inv = cnt_part[0] ? 1.0 / (double)cnt_part[0] : 0.0;
   const int p = threadIdx.x;
-  if (p > NPARAM) return;
+  if (p > NPARAM + 1) return;
   double acc = 0.0;
   if (p < NW1) {
     const int k = p / NIN, i = p % NIN;
-    for (uint32_t s = 0; s < nsamp; ++s)
-      acc += (double)ws[(uint64_t)s * ROW + k] * (double)feat[(uint64_t)s * NIN + i];
+    for (uint32_t s = 0; s < m; ++s) acc += (double)srow[s * ROW + k] * (double)sfeat[s * NIN + i];
   } else if (p < NW1 + NB1) {
     const int k = p - NW1;
-    for (uint32_t s = 0; s < nsamp; ++s) acc += (double)ws[(uint64_t)s * ROW + k];
+    for (uint32_t s = 0; s < m; ++s) acc += (double)srow[s * ROW + k];
   } else if (p < NW1 + NB1 + NW2) {
     const int o = (p - NW1 - NB1) / NH, k = (p - NW1 - NB1) % NH;
-    for (uint32_t s = 0; s < nsamp; ++s)
-      acc += (double)ws[(uint64_t)s * ROW + 2 * NH + o] * (double)ws[(uint64_t)s * ROW + NH + k];
+    for (uint32_t s = 0; s < m; ++s)
+      acc += (double)srow[s * ROW + 2 * NH + o] * (double)srow[s * ROW + NH + k];
   } else if (p < NPARAM) {
     const int o = p - NW1 - NB1 - NW2;
-    for (uint32_t s = 0; s < nsamp; ++s) acc += (double)ws[(uint64_t)s * ROW + 2 * NH + o];
+    for (uint32_t s = 0; s < m; ++s) acc += (double)srow[s * ROW + 2 * NH + o];
+  } else if (p == NPARAM) {
+    for (uint32_t s = 0; s < m; ++s) acc += (double)srow[s * ROW + 2 * NH + NOUT];
   } else {
-    for (uint32_t s = 0; s < nsamp; ++s) acc += (double)ws[(uint64_t)s * ROW + 2 * NH + NOUT];
+    for (uint32_t s = 0; s < m; ++s) acc += slab[s] < NOUT ? 1.0 : 0.0;
   }
+  part[(uint64_t)blockIdx.x * PSTRIDE + p] = acc;
+}
+
+__global__ __launch_bounds__(704) void k_mlp_reduce(uint32_t ngroups,
+                                                   const double* __restrict__ part,
+                                                   float* __restrict__ grad,
+                                                   float* __restrict__ loss) {
+  __shared__ double cnt;
+  const int p = threadIdx.x;
+  if (p == 0) {
+    double c = 0.0;
+    for (uint32_t g = 0; g < ngroups; ++g) c += part[(uint64_t)g * PSTRIDE + NPARAM + 1];
+    cnt = c;
+  }
+  __syncthreads();
+  if (p > NPARAM) return;
+  double acc = 0.0;
+  for (uint32_t g = 0; g < ngroups; ++g) acc += part[(uint64_t)g * PSTRIDE + p];
+  const double inv = cnt > 0.0 ? 1.0 / cnt : 0.0;
   if (p < NPARAM) grad[p] = (float)(acc * inv);
   else *loss = (float)(acc * inv);
 }
@@ -124,13 +151,23 @@ __global__ void k_mlp_adam(float* __restrict__ w, const float* __restrict__ g,
   w[p] = w[p] - lr * (mi / bc1) / (sqrtf(vi / bc2) + 1e-8f);
 }
 
+size_t mlp_workspace_bytes() {
+  return (size_t)MLP_MAX_BATCH * MLP_ROW * sizeof(float) +
+         (size_t)(MLP_MAX_BATCH / GROUP) * PSTRIDE * sizeof(double);
+}
+
 hipError_t launch_mlp_grad(const float* w, const int8_t* feat, const uint8_t* label,
                            uint32_t nsamp, float* ws, float* grad, float* loss, hipStream_t st) {
+  // ws: per-sample rows, then the per-group partial sums (8-byte aligned)
+  double* part = (double*)(ws + (size_t)MLP_MAX_BATCH * MLP_ROW);
+  const uint32_t ngroups = (nsamp + GROUP - 1) / GROUP;
   if (nsamp) {
     hipLaunchKernelGGL(k_mlp_fwdbwd, dim3((nsamp + 255) / 256), dim3(256), 0, st, w, feat, label,
                        nsamp, ws);
+    hipLaunchKernelGGL(k_mlp_partial, dim3(ngroups), dim3(704), 0, st, feat, label, nsamp, ws,
+                       part);
   }
-  hipLaunchKernelGGL(k_mlp_reduce, dim3(1), dim3(1024), 0, st, feat, label, nsamp, ws, grad, loss);
+  hipLaunchKernelGGL(k_mlp_reduce, dim3(1), dim3(704), 0, st, ngroups, part, grad, loss);
   return hipGetLastError();
 }
 
