@@ -75,7 +75,11 @@ typedef struct gz_graph gz_graph;
  * 128|256|512|1024 (0 = tuned/default; 1024 is built for fp32 1D work only, and
  * it or a size whose LDS staging exceeds the device's per-workgroup limit gives
  * GZ_EUNSUPPORTED) and grid (persistent workgroups, 0 = default) never change
- * the bytes.  mode 0 = 1D blocks, 1 = 8x8 tiles (block_len 64,
+ * the bytes.  threads 64 selects the per-wave kernels, in which each wave
+ * codes whole 4096-element superblocks on its own (grid ignored): 1D
+ * decompression of either type, fp32 1D compression and the fused step;
+ * GZ_EUNSUPPORTED elsewhere.  They are also the default for those calls
+ * when no shape is given or tuned.  mode 0 = 1D blocks, 1 = 8x8 tiles (block_len 64,
  * nx = row length, multiple of 8, n a multiple of 8*nx); select (mode 1):
  * 0 = int8 MLP selector, 1 = exhaustive trial, 2 = always L1D. */
 typedef struct {
@@ -226,7 +230,10 @@ gz_status gz_scatter_decompress(gz_ctx* ctx, const void* d_packed,
  * cost") share one grid.  op selects compress, decompress, fused step or
  * decode-and-accumulate (fp32 only, as gz_decompress_add); p gives
  * threads/grid only (0: the shapes gz_tune_batch stored for this op and
- * element-type mix, else defaults). */
+ * element-type mix, else defaults).  A compress or fused batch whose jobs
+ * are all fp32 with the same block length and superblock count runs on the
+ * per-wave kernels by default (threads 64; refused with GZ_EUNSUPPORTED for
+ * other batches). */
 gz_status gz_batch(gz_ctx* ctx, gz_op op, const gz_request* h_reqs,
                    uint32_t nreq, const gz_params* p, gz_stream_t stream);
 
@@ -251,9 +258,10 @@ gz_status gz_graph_create(gz_plan* const* plans, uint32_t nplans,
 gz_status gz_graph_launch(gz_graph* graph, gz_stream_t stream);
 void gz_graph_destroy(gz_graph* graph);
 
-/* The autotuner (block size and threads per block, the benchmark spec's batching
- * extension, for the small-input under-use of Sec. 3.2.2).  Times the launch
- * shapes (threads, grid) of compress and decompress for (dtype, block_len)
+/* The autotuner (block size and threads per block, the batching extension
+ * for the small-input under-use of Sec. 3.2.2).  Times the launch shapes
+ * (threads, grid; threads 64 = the per-wave kernels) of compress and
+ * decompress for (dtype, block_len)
  * on the caller's sample d_sample[0..n) (read only) and stores the fastest
  * in the context; with block_len 0 it tries 32, 64 and 128 and stores the
  * fastest as the block length of requests that give 0.  d_work is a
@@ -269,7 +277,8 @@ gz_status gz_tune(gz_ctx* ctx, gz_dtype dtype, uint32_t block_len, const void* d
 
 /* Times the caller's own batch (op compress, decompress or fused step; the
  * accumulate op updates in place and is refused with GZ_EINVAL) over
- * threads {128..1024} x grid {1, 2, occupancy, 2 x occupancy} x CUs, and
+ * threads {128..1024} x grid {1, 2, occupancy, 2 x occupancy} x CUs, plus
+ * the per-wave kernels where the batch qualifies (as gz_batch), and
  * stores the fastest shape for (op, batch holds fp64) in the context, where
  * gz_batch and gz_plan_create take it.  Runs the batch 4 times per shape in
  * place on `stream` (outputs are rewritten with the same bytes) and waits

@@ -108,6 +108,8 @@ struct gz_plan {
   uint32_t njobs = 0;  // uniform batch: the kernels derive (job, strip)
   uint32_t tpb = 0, grid = 0;
   bool wide = false;
+  bool wave = false;  // per-wave encoding kernels (total = njobs x rounds)
+  uint32_t log2L = 5;
 };
 
 struct gz_graph {
@@ -182,11 +184,14 @@ bool tile_mode(const gz_params* p);
 // Operations 0-3 as gz_op; decode-and-accumulate (3) shares decoding's tuning.
 uint32_t tune_op(uint32_t op) { return op == 3 ? 1u : op; }
 
+// threads = 64 (one wave) asks for the per-wave kernels.
+constexpr uint32_t WAVE_TPB = 64;
+
 uint32_t pick_tpb(const gz_ctx* c, uint32_t op, uint32_t dt, uint32_t L, const gz_params* p) {
   if (p && p->threads) return p->threads;
   if (!tile_mode(p)) {
     const Tuned& t = c->tuned[tune_op(op)][dt][log2_of(L) - 5];
-    if (t.tpb) return t.tpb;
+    if (t.tpb && t.tpb != WAVE_TPB) return t.tpb;
   }
   if (dt != GZ_F32 || tile_mode(p)) return 256;
   for (uint32_t t = tune_op(op) == 1 ? 512u : 1024u; t > 256; t /= 2)
@@ -219,11 +224,14 @@ uint32_t pick_tile_grid(const gz_ctx* c, uint32_t op, uint32_t tpb, uint64_t str
   return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(g, strips));
 }
 
-bool tpb_ok(uint32_t t) { return t == 0 || t == 128 || t == 256 || t == 512 || t == 1024; }
+bool tpb_ok(uint32_t t) {
+  return t == 0 || t == WAVE_TPB || t == 128 || t == 256 || t == 512 || t == 1024;
+}
 
-// The kernel is built for tpb threads (1024 only for fp32 1D kernels) and
-// the workgroup's LDS fits the device (512-thread fp64 strips may not).
+// The strip kernel is built for tpb threads (1024 only for fp32 1D kernels)
+// and the workgroup's LDS fits the device (512-thread fp64 strips may not).
 bool tpb_fits(const gz_ctx* c, bool wide, bool tile, uint32_t tpb) {
+  if (tpb < 128) return false;
   if (tpb > ((wide || tile) ? gzk::MAX_TPB_WIDE : gzk::MAX_TPB)) return false;
   return gzk::lds_bytes(wide ? 1u : 0u, tpb) <= c->lds_max;
 }
@@ -241,6 +249,22 @@ bool params_ok(const gz_params* p, uint32_t& L) {
 }
 
 bool tile_mode(const gz_params* p) { return p && p->mode == 1; }
+
+// Per-wave kernels exist for 1D decoding of either type (op 1) and fp32 1D
+// encoding and the fused step (ops 0, 2), and need their LDS.
+bool wave_fits(const gz_ctx* c, uint32_t op, uint32_t dt) {
+  if (op == 1) return gzk::wave_decode_lds(dt) <= c->lds_max;
+  return (op == 0 || op == 2) && dt == GZ_F32 && gzk::wave_encode_lds() <= c->lds_max;
+}
+
+// Whether a single 1D call takes the per-wave kernel: asked for (threads
+// 64), tuned, or by default (no threads, grid or tuned shape).
+bool wave_wanted(const gz_ctx* c, uint32_t op, uint32_t dt, uint32_t L, const gz_params* p) {
+  if (p && p->threads) return p->threads == WAVE_TPB;
+  if (p && p->grid) return false;
+  const Tuned& t = c->tuned[tune_op(op)][dt][log2_of(L) - 5];
+  return t.tpb ? t.tpb == WAVE_TPB : true;
+}
 
 gz_status hip_status(hipError_t e) { return e == hipSuccess ? GZ_OK : GZ_EHIP; }
 
@@ -356,10 +380,31 @@ uint32_t batch_tpb(const gz_ctx* c, gz_op op, const gz_request* r, uint32_t nreq
                    const gz_params* p, bool& wide) {
   wide = false;
   for (uint32_t j = 0; j < nreq; ++j) wide = wide || r[j].dtype == GZ_F64;
-  if (p && p->threads) return p->threads;
+  if (p && p->threads && p->threads != WAVE_TPB) return p->threads;
   const Tuned& t = c->batch_tuned[op][wide ? 1 : 0];
-  if (t.tpb) return t.tpb;
+  if (t.tpb && t.tpb != WAVE_TPB) return t.tpb;
   return pick_tpb(c, op, wide ? GZ_F64 : GZ_F32, 32, nullptr);
+}
+
+// A batch the per-wave encoding kernels take: compression or the fused
+// step, every job fp32 with the same block length and superblock count.
+bool batch_wave_ok(const gz_ctx* c, gz_op op, const std::vector<Job>& jobs) {
+  if ((op != GZ_OP_COMPRESS && op != GZ_OP_FUSED) || jobs.empty() || !wave_fits(c, op, GZ_F32))
+    return false;
+  for (const Job& J : jobs)
+    if (J.dtype != GZ_F32 || J.log2L != jobs[0].log2L || J.NS != jobs[0].NS || J.NS == 0)
+      return false;
+  const uint64_t total = jobs.size() * gzk::wave_rounds(jobs[0].NS);
+  return total <= c->max_strips && total < (1ull << 32);
+}
+
+// Whether a batch takes the per-wave kernels when it can: asked for
+// (threads 64), tuned, or by default.
+bool batch_wave_wanted(const gz_ctx* c, gz_op op, const gz_params* p) {
+  if (p && p->threads) return p->threads == WAVE_TPB;
+  if (p && p->grid) return false;
+  const Tuned& t = c->batch_tuned[op][0];
+  return t.tpb ? t.tpb == WAVE_TPB : true;
 }
 
 uint32_t batch_grid(const gz_ctx* c, gz_op op, bool wide, uint32_t tpb, uint64_t total,
@@ -538,6 +583,28 @@ gz_status compress_impl(gz_ctx* c, const void* d_in, uint64_t n, gz_dtype dtype,
   memset(&J, 0, sizeof J);
   J.dtype = dtype;
   if (!set_bound(J, dtype, eb)) return GZ_EINVAL;
+  // per-wave encoding takes one look-back word per round of 8 superblocks; a
+  // stream with more rounds than the workspace has words falls back to
+  // strips unless the caller asked for waves
+  if (!tile_mode(p) && n && wave_wanted(c, 0, dtype, L, p) && wave_fits(c, 0, dtype)) {
+    set_geom(J, n, L, gzk::MAX_TPB);
+    if (gzk::wave_rounds(J.NS) <= c->max_strips) {
+      J.in = job_ptr(d_in);
+      J.out = job_ptr(d_out);
+      J.out_bytes = job_ptr((unsigned long long*)d_out_bytes);
+      return hip_status(gzk::launch_encode_wave(0, nullptr, J, 1,
+                                                (uint32_t)gzk::wave_rounds(J.NS), J.log2L,
+                                                c->ctl(), (uint32_t)c->cus,
+                                                (hipStream_t)stream));
+    }
+    if (p && p->threads == WAVE_TPB) return GZ_ENOSPC;
+  }
+  gz_params q;  // an empty stream asked for waves: one default strip writes its header
+  if (!n && p && p->threads == WAVE_TPB && !tile_mode(p) && wave_fits(c, 0, dtype)) {
+    q = *p;
+    q.threads = q.grid = 0;
+    p = &q;
+  }
   const uint32_t tpb = pick_tpb(c, 0, dtype, L, p);
   if (!tpb_fits(c, dtype == GZ_F64, tile_mode(p), tpb)) return GZ_EUNSUPPORTED;
   set_geom(J, n, L, tpb);
@@ -579,6 +646,14 @@ gz_status gz_decompress(gz_ctx* c, const void* d_in, uint64_t in_bytes, uint64_t
   Job J;
   memset(&J, 0, sizeof J);
   J.dtype = dtype;
+  if (!tile_mode(p) && wave_wanted(c, 1, dtype, L, p) && wave_fits(c, 1, dtype)) {
+    set_geom(J, n, L, gzk::MAX_TPB);
+    J.in = job_ptr(d_in);
+    J.in_bytes = in_bytes;
+    J.out = job_ptr(d_out);
+    return hip_status(gzk::launch_decompress_wave(J, c->ctl(), (uint32_t)c->cus,
+                                                  (hipStream_t)stream));
+  }
   const uint32_t tpb = pick_tpb(c, 1, dtype, L, p);
   if (!tpb_fits(c, dtype == GZ_F64, tile_mode(p), tpb)) return GZ_EUNSUPPORTED;
   set_geom(J, n, L, tpb);
@@ -614,15 +689,30 @@ gz_status gz_fused_reduce_step(gz_ctx* c, const void* d_cmp_in, uint64_t in_byte
   memset(&J, 0, sizeof J);
   J.dtype = GZ_F32;
   if (!set_bound(J, GZ_F32, eb)) return GZ_EINVAL;
-  const uint32_t tpb = pick_tpb(c, 2, GZ_F32, L, p);
-  if (!tpb_fits(c, false, false, tpb)) return GZ_EUNSUPPORTED;
-  set_geom(J, n, L, tpb);
-  if (J.nstrips > c->max_strips) return GZ_ENOSPC;
   J.in = job_ptr(d_cmp_in);
   J.in_bytes = in_bytes;
   J.local = job_ptr(d_local);
   J.out = job_ptr(d_cmp_out);
   J.out_bytes = job_ptr((unsigned long long*)d_out_bytes);
+  if (n && wave_wanted(c, 2, GZ_F32, L, p) && wave_fits(c, 2, GZ_F32)) {
+    set_geom(J, n, L, gzk::MAX_TPB);
+    if (gzk::wave_rounds(J.NS) <= c->max_strips)
+      return hip_status(gzk::launch_encode_wave(2, nullptr, J, 1,
+                                                (uint32_t)gzk::wave_rounds(J.NS), J.log2L,
+                                                c->ctl(), (uint32_t)c->cus,
+                                                (hipStream_t)stream));
+    if (p && p->threads == WAVE_TPB) return GZ_ENOSPC;
+  }
+  gz_params q;  // an empty stream asked for waves: one default strip writes its header
+  if (!n && p && p->threads == WAVE_TPB) {
+    q = *p;
+    q.threads = q.grid = 0;
+    p = &q;
+  }
+  const uint32_t tpb = pick_tpb(c, 2, GZ_F32, L, p);
+  if (!tpb_fits(c, false, false, tpb)) return GZ_EUNSUPPORTED;
+  set_geom(J, n, L, tpb);
+  if (J.nstrips > c->max_strips) return GZ_ENOSPC;
   const uint32_t grid = pick_grid(c, 2, GZ_F32, L, tpb, J.nstrips, p);
   return hip_status(gzk::launch_single(2, J, c->ctl(), tpb, grid, (hipStream_t)stream));
 }
@@ -756,9 +846,16 @@ gz_status gz_batch(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t nreq,
   std::vector<uint32_t> map;
   gz_status r = build_requests(c, op, h_reqs, nreq, tpb, jobs, map);
   if (r != GZ_OK) return r;
+  const bool wave = !wide && batch_wave_wanted(c, op, p) && batch_wave_ok(c, op, jobs);
+  if (p && p->threads == WAVE_TPB && !wave) return GZ_EUNSUPPORTED;
   hipStream_t st = (hipStream_t)stream;
   r = stage_upload(c, jobs, map, st);
   if (r != GZ_OK) return r;
+  if (wave)
+    return hip_status(gzk::launch_encode_wave(
+        (uint32_t)op, c->d_jobs, Job(), (uint32_t)jobs.size(),
+        (uint32_t)(jobs.size() * gzk::wave_rounds(jobs[0].NS)), jobs[0].log2L, c->ctl(),
+        (uint32_t)c->cus, st));
   const uint64_t total = map.size() / 2;
   const uint32_t g = batch_grid(c, op, wide, tpb, total, p);
   return hip_status(gzk::launch_batch((uint32_t)op, c->d_jobs, c->d_map, uniform_jobs(jobs),
@@ -778,6 +875,8 @@ gz_status gz_plan_create(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t
   std::vector<uint32_t> map;
   gz_status r = build_requests(c, op, h_reqs, nreq, tpb, jobs, map);
   if (r != GZ_OK) return r;
+  const bool wave = !wide && batch_wave_wanted(c, op, p) && batch_wave_ok(c, op, jobs);
+  if (p && p->threads == WAVE_TPB && !wave) return GZ_EUNSUPPORTED;
   // a range released by gz_plan_destroy may still be read by a launch in
   // flight: the device finishes its work before the arena is written
   if (hipDeviceSynchronize() != hipSuccess) return GZ_EHIP;
@@ -804,6 +903,12 @@ gz_status gz_plan_create(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t
   pl->tpb = tpb;
   pl->wide = wide;
   pl->grid = batch_grid(c, op, wide, tpb, pl->total, p);
+  if (wave) {
+    pl->wave = true;
+    pl->njobs = (uint32_t)jobs.size();
+    pl->total = (uint32_t)(jobs.size() * gzk::wave_rounds(jobs[0].NS));
+    pl->log2L = jobs[0].log2L;
+  }
   c->live_plans.push_back(pl);
   if (hipMemcpy(pl->d_jobs, jobs.data(), jobs.size() * sizeof(Job), hipMemcpyHostToDevice) !=
           hipSuccess ||
@@ -817,6 +922,10 @@ gz_status gz_plan_create(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t
 
 gz_status gz_plan_launch(gz_plan* pl, gz_stream_t stream) {
   if (!pl || !pl->ctx) return GZ_EINVAL;
+  if (pl->wave)
+    return hip_status(gzk::launch_encode_wave(pl->op, pl->d_jobs, Job(), pl->njobs, pl->total,
+                                              pl->log2L, pl->ctx->ctl(),
+                                              (uint32_t)pl->ctx->cus, (hipStream_t)stream));
   return hip_status(gzk::launch_batch(pl->op, pl->d_jobs, pl->d_map, pl->njobs, pl->total,
                                       pl->ctx->ctl(),
                                       pl->tpb, pl->grid, pl->wide, (hipStream_t)stream));
@@ -970,10 +1079,18 @@ gz_status gz_tune(gz_ctx* c, gz_dtype dt, uint32_t block_len, const void* d_samp
                L, (unsigned long long)n);
       uint32_t tpb = 0, grid = 0;
       float ms = 0;
-      if (cache_lookup(cache_path, keyb, tpb, grid) && tpb_fits(c, dt == GZ_F64, false, tpb)) {
+      const bool wave_ok = wave_fits(c, op, dt);
+      if (cache_lookup(cache_path, keyb, tpb, grid) &&
+          (tpb_fits(c, dt == GZ_F64, false, tpb) || (tpb == WAVE_TPB && wave_ok))) {
         r = time_op(c, op, d_sample, y, s, cap, nb, n, dt, L, tpb, grid, st, e0, e1, ms);
       } else {
         float bms = 1e30f;
+        if (wave_ok) {  // the per-wave kernel (its grid is its own)
+          r = time_op(c, op, d_sample, y, s, cap, nb, n, dt, L, WAVE_TPB, (uint32_t)c->cus, st,
+                      e0, e1, bms);
+          tpb = WAVE_TPB;
+          grid = (uint32_t)c->cus;
+        }
         const uint32_t tpbs[4] = {128, 256, 512, 1024};
         for (uint32_t ti = 0; r == GZ_OK && ti < 4; ++ti) {
           if (!tpb_fits(c, dt == GZ_F64, false, tpbs[ti])) continue;
@@ -1030,18 +1147,30 @@ gz_status gz_tune_batch(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t 
            (unsigned)op, wide ? 1u : 0u, nreq, (unsigned long long)elems);
   uint32_t tpb = 0, grid = 0;
   gz_status r = GZ_OK;
-  if (!(cache_lookup(cache_path, keyb, tpb, grid) && tpb_fits(c, wide, false, tpb))) {
+  // the per-wave kernels are a candidate where the batch qualifies
+  bool wave_ok = false;
+  if (!wide) {
+    std::vector<Job> jobs;
+    std::vector<uint32_t> map;
+    r = build_requests(c, op, h_reqs, nreq, gzk::MAX_TPB, jobs, map);
+    if (r != GZ_OK) return r;
+    wave_ok = batch_wave_ok(c, op, jobs);
+  }
+  if (!(cache_lookup(cache_path, keyb, tpb, grid) &&
+        (tpb_fits(c, wide, false, tpb) || (tpb == WAVE_TPB && wave_ok)))) {
     hipStream_t st = (hipStream_t)stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) r = GZ_EHIP;
     float bms = 1e30f;
-    const uint32_t tpbs[4] = {128, 256, 512, 1024};
-    for (uint32_t ti = 0; r == GZ_OK && ti < 4; ++ti) {
-      if (!tpb_fits(c, wide, false, tpbs[ti])) continue;
-      const int occ = gzk::occupancy_blocks(gzk::OCC_BATCH + (uint32_t)op, wide, 5, tpbs[ti]);
+    const uint32_t tpbs[5] = {WAVE_TPB, 128, 256, 512, 1024};
+    for (uint32_t ti = 0; r == GZ_OK && ti < 5; ++ti) {
+      const bool wv = tpbs[ti] == WAVE_TPB;
+      if (wv ? !wave_ok : !tpb_fits(c, wide, false, tpbs[ti])) continue;
+      const int occ =
+          wv ? 1 : gzk::occupancy_blocks(gzk::OCC_BATCH + (uint32_t)op, wide, 5, tpbs[ti]);
       const uint32_t grids[4] = {(uint32_t)c->cus, 2u * c->cus, (uint32_t)(c->cus * occ),
                                  (uint32_t)(c->cus * occ * 2)};
-      for (uint32_t gi = 0; r == GZ_OK && gi < 4; ++gi) {
+      for (uint32_t gi = 0; r == GZ_OK && gi < (wv ? 1u : 4u); ++gi) {
         const gz_params p = {0, tpbs[ti], grids[gi], 0, 0, 0};
         r = gz_batch(c, op, h_reqs, nreq, &p, st);  // warm-up
         if (r == GZ_OK && hipEventRecord(e0, st) != hipSuccess) r = GZ_EHIP;

@@ -18,6 +18,22 @@ size_t lds_bytes(uint32_t wide, uint32_t tpb);
 hipError_t launch_batch(uint32_t op, const Job* d_jobs, const uint32_t* d_strip_job,
                         uint32_t njobs, uint32_t total, const Ctl& C, uint32_t tpb,
                         uint32_t grid, bool wide, hipStream_t st);
+// Per-wave decoding of one stream (mode 0): every wave decodes whole
+// superblocks, assigned statically; grid = min(CUs, superblocks per wave).
+hipError_t launch_decompress_wave(const Job& J, const Ctl& C, uint32_t cus, hipStream_t st);
+size_t wave_decode_lds(uint32_t dtype);  // its workgroup's LDS bytes
+// Per-wave fp32 1D encoding (op 0) or fused step (op 2): every wave encodes
+// whole superblocks, a workgroup's waves the 8 of a round (one chain
+// element).  d_jobs null: the one job J, total = rounds_of(J.NS); else njobs
+// jobs of the same superblock count and block length 2^log2L in device
+// memory, total = njobs * rounds_of(NS), round ticket t = round t / njobs
+// of job t % njobs.
+hipError_t launch_encode_wave(uint32_t op, const Job* d_jobs, const Job& J, uint32_t njobs,
+                              uint32_t total, uint32_t log2L, const Ctl& C, uint32_t cus,
+                              hipStream_t st);
+size_t wave_encode_lds();  // its workgroup's LDS bytes
+constexpr uint64_t WAVE_ROUND = 8;  // superblocks per round of the per-wave encoder
+inline uint64_t wave_rounds(uint64_t NS) { return (NS + WAVE_ROUND - 1) / WAVE_ROUND; }
 hipError_t launch_quantize(const void* x, uint64_t n, const Job& J, int32_t* q, uint8_t* fail,
                            hipStream_t st);
 // mode 1 (8x8 tiles, fp32): op 0 compress, 1 decompress

@@ -288,13 +288,16 @@ __device__ __forceinline__ void publish_agg(const Ctl& C, uint64_t gs, uint64_t 
   st_agent(C.status + gs, sw_pack(gs == chain0 ? 2 : 1, ep, agg));
 }
 
-// Decoupled look-back run by wave 0 after publish_agg: returns the exclusive
-// prefix (dwords) of strip gs within its chain and publishes its inclusive
-// prefix.  One probe reads LB_SUB x 64 predecessors (LB_SUB independent loads
-// per lane); sub-windows resolved before a not-yet-published word are added
-// in before the probe is retried from there.
+// Decoupled look-back run by one wave after publish_agg: returns the
+// exclusive prefix (dwords) of strip gs within its chain and publishes its
+// inclusive prefix.  One probe reads SUB x 64 predecessors (SUB independent
+// loads per lane); sub-windows resolved before a not-yet-published word are
+// added in before the probe is retried from there.  Strips probe 256 words;
+// the per-wave encoder, with eight times as many chain elements, probes 64
+// (its status-word reads would otherwise rival its payload traffic).
 constexpr int LB_SUB = 4;
 
+template <int SUB = LB_SUB, bool PUBLISH = true>
 __device__ uint64_t lookback(const Ctl& C, uint64_t gs, uint64_t chain0, uint32_t ep,
                              uint64_t agg, bool& timeout) {
   const int lane = __lane_id();
@@ -304,19 +307,19 @@ __device__ uint64_t lookback(const Ctl& C, uint64_t gs, uint64_t chain0, uint32_
   uint32_t spins = 0;
   uint64_t t0 = 0;
   for (;;) {
-    uint32_t flag[LB_SUB];
-    uint64_t val[LB_SUB];
+    uint32_t flag[SUB];
+    uint64_t val[SUB];
     // every load is issued before any is used: lanes before the chain's
     // start read its first word (a load under a divergent branch is merged
     // by register copies that wait for it at once, one round trip per load)
-    uint64_t w[LB_SUB];
+    uint64_t w[SUB];
 #pragma unroll
-    for (int m = 0; m < LB_SUB; ++m) {
+    for (int m = 0; m < SUB; ++m) {
       const int64_t idx = top - 64 * m - lane;
       w[m] = ld_agent(C.status + (idx >= (int64_t)chain0 ? idx : (int64_t)chain0));
     }
 #pragma unroll
-    for (int m = 0; m < LB_SUB; ++m) {
+    for (int m = 0; m < SUB; ++m) {
       const int64_t idx = top - 64 * m - lane;
       const bool cur = (uint32_t)((w[m] >> 34) & 0x0FFFFFFFu) == (ep & 0x0FFFFFFFu);
       const bool in_chain = idx >= (int64_t)chain0;
@@ -327,7 +330,7 @@ __device__ uint64_t lookback(const Ctl& C, uint64_t gs, uint64_t chain0, uint32_
     int resolved = 0;   // sub-windows fully added in
     bool done = false, wait = false;
 #pragma unroll
-    for (int m = 0; m < LB_SUB; ++m) {
+    for (int m = 0; m < SUB; ++m) {
       if (!done && !wait) {
         const uint64_t pm = __ballot(flag[m] == 2);
         const uint64_t zm = __ballot(flag[m] == 0);
@@ -354,7 +357,7 @@ __device__ uint64_t lookback(const Ctl& C, uint64_t gs, uint64_t chain0, uint32_
       __builtin_amdgcn_s_sleep(1);
     }
   }
-  if (lane == 0) st_agent(C.status + gs, sw_pack(2, ep, timeout ? 0 : excl + agg));
+  if (PUBLISH && lane == 0) st_agent(C.status + gs, sw_pack(2, ep, timeout ? 0 : excl + agg));
   return excl;
 }
 
@@ -716,10 +719,12 @@ struct LaneCode {
 // Mode 0: 1D blocks of L consecutive elements, L1D prediction.  KEEP (fp32
 // fused step): a block whose quantisation fails puts its values' bits in a[]
 // for the RAW payload, from the lane's LDS segment, where the fused step
-// stored them (they are not in global memory).
+// stored them (they are not in global memory); keep_row: that segment, if
+// not the strip layout's.
 template <typename T, int L, bool FULL, bool KEEP = false>
 __device__ __forceinline__ void analyze_1d(const Job& J, uint64_t seg, uint32_t w,
-                                           const T (&v)[32], uint32_t vcnt, LaneCode& lc) {
+                                           const T (&v)[32], uint32_t vcnt, LaneCode& lc,
+                                           const uint32_t* keep_row = nullptr) {
   constexpr int LPB = L / 32;
   constexpr uint32_t EW = sizeof(T) / 4;
   const uint64_t b = seg / LPB;
@@ -747,7 +752,16 @@ __device__ __forceinline__ void analyze_1d(const Job& J, uint64_t seg, uint32_t 
     // a RAW block stores the values themselves: the fused step left them in
     // the lane's own LDS segment (so v[] need not outlive the quantisation)
     float u[32];
-    lane_from_lds<float>(u);
+    if (keep_row) {
+      const f4u* p = (const f4u*)keep_row;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const f4u r = p[k];
+        u[4 * k] = r.x; u[4 * k + 1] = r.y; u[4 * k + 2] = r.z; u[4 * k + 3] = r.w;
+      }
+    } else {
+      lane_from_lds<float>(u);
+    }
 #pragma unroll
     for (int i = 0; i < 32; ++i) a[i] = (FULL || i < (int)vcnt) ? __float_as_uint(u[i]) : 0u;
   } else {
@@ -1054,6 +1068,25 @@ __device__ __forceinline__ void fused_raw_stage(const Job& J, const FusedSrc& fs
   }
 }
 
+// Word i (0..15) of the stream header for a payload of `payload` bytes.
+__device__ __forceinline__ uint32_t hdr_word(const Job& J, uint32_t i, uint64_t payload) {
+  const unsigned long long ebits = (unsigned long long)__double_as_longlong(J.eb);
+  switch (i) {
+    case 0: return 0x31435A47u;
+    case 1: return 1u | (J.dtype << 16) | (J.log2L << 24);
+    case 2: return (uint32_t)J.n;
+    case 3: return (uint32_t)(J.n >> 32);
+    case 4: return (uint32_t)ebits;
+    case 5: return (uint32_t)(ebits >> 32);
+    case 6: return (uint32_t)payload;
+    case 7: return (uint32_t)(payload >> 32);
+    case 8: return J.mode;
+    case 9: return J.nx;
+    case 10: return SUPER;
+    default: return 0u;
+  }
+}
+
 template <typename T, int L, int MODE, bool FUSED, bool FULL>
 __device__ void emit_strip(const Job& J, uint64_t s, uint64_t gs, const Ctl& C, Smem& sm,
                            uint32_t vcnt, const LaneCode& lc, const FusedSrc* fs, bool skip,
@@ -1148,23 +1181,7 @@ __device__ void emit_strip(const Job& J, uint64_t s, uint64_t gs, const Ctl& C, 
   // the last strip completes the header and the size outputs
   if (s == J.nstrips - 1 && tid < 16) {
     const uint64_t payload = 4 * (sm.excl + total - pj);
-    unsigned long long ebits = (unsigned long long)__double_as_longlong(J.eb);
-    uint32_t wv = 0;
-    switch (tid) {
-      case 0: wv = 0x31435A47u; break;
-      case 1: wv = 1u | (J.dtype << 16) | (J.log2L << 24); break;
-      case 2: wv = (uint32_t)J.n; break;
-      case 3: wv = (uint32_t)(J.n >> 32); break;
-      case 4: wv = (uint32_t)ebits; break;
-      case 5: wv = (uint32_t)(ebits >> 32); break;
-      case 6: wv = (uint32_t)payload; break;
-      case 7: wv = (uint32_t)(payload >> 32); break;
-      case 8: wv = J.mode; break;
-      case 9: wv = J.nx; break;
-      case 10: wv = SUPER; break;
-      default: wv = 0; break;
-    }
-    ((uint32_t*)base8)[tid] = wv;
+    ((uint32_t*)base8)[tid] = hdr_word(J, tid, payload);
     if (tid == 0) {
       if (J.out_bytes) *J.out_bytes = J.pay_off + payload;
       if (J.chunk_off) *J.chunk_off = J.fixed_off + 4 * pj;
@@ -1608,6 +1625,755 @@ __device__ __forceinline__ void decompress_tp_one(const Job& J, uint64_t s, cons
   else decompress_tp_body<T, L, false>(J, s, C, sm, nxt);
 }
 
+// ---------------------------------------------------------- per-wave decode
+// A wave decodes whole 4096-element superblocks on its own: a superblock's
+// payload offset is its table entry, so waves need no scan across each
+// other, no ticket and no workgroup barrier, and the phases of different
+// waves (loads, unpacking, stores) overlap freely.  Superblock i goes to
+// wave i mod W (W waves in the grid): decoding has no dependency between
+// superblocks, so this static assignment needs no co-residency.  A wave's
+// LDS region holds the superblock's payload, then its decoded values in the
+// padded segment layout for coalesced stores.  Lane l decodes segments l and
+// 64 + l of the superblock.
+template <typename T>
+struct WaveDec {
+  static constexpr uint32_t WAVES = sizeof(T) == 4 ? 8 : 4;               // per workgroup
+  static constexpr uint32_t REGION = 2 * 64 * seg_stride<T>() + 8;         // dwords per wave
+};
+
+// LDS written by some lanes of the wave is read by others: the wave's LDS
+// operations complete in order, and the compiler may not move memory
+// accesses across this point.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+  __builtin_amdgcn_wave_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// The stream header against the job, by one wave: ok, payload dwords and step.
+template <typename T>
+__device__ __forceinline__ bool wave_header(const Job& J, const uint8_t* in, uint64_t& paydw,
+                                            T& t) {
+  const uint32_t lane = __lane_id();
+  const bool readable = J.in_bytes >= HDR;
+  const uint32_t wv = (lane < 16 && readable) ? ((const uint32_t*)in)[lane] : 0u;
+  bool ok = true;
+  switch (lane) {
+    case 0: ok = wv == 0x31435A47u; break;
+    case 1: ok = wv == (1u | (J.dtype << 16) | (J.log2L << 24)); break;
+    case 2: ok = wv == (uint32_t)J.n; break;
+    case 3: ok = wv == (uint32_t)(J.n >> 32); break;
+    case 8: ok = wv == J.mode; break;
+    case 9: ok = wv == J.nx; break;
+    case 10: ok = wv == SUPER; break;
+    case 4: case 5: case 6: case 7: ok = true; break;
+    default: ok = lane < 16 ? wv == 0u : true; break;
+  }
+  const bool allok = __ballot(ok) == ~0ull;
+  const uint32_t e0 = __shfl(wv, 4), e1 = __shfl(wv, 5), p0 = __shfl(wv, 6), p1 = __shfl(wv, 7);
+  const double eb = __longlong_as_double((long long)(((uint64_t)e1 << 32) | e0));
+  const uint64_t payload = ((uint64_t)p1 << 32) | p0;
+  bool good = readable && allok && (eb > 0.0) && isfinite(eb);
+  const float t32 = (float)(2.0 * eb);
+  const double t64 = 2.0 * eb;
+  if (sizeof(T) == 4) good = good && isfinite(t32) && t32 != 0.0f;
+  else good = good && isfinite(t64) && t64 != 0.0;
+  good = good && (payload % 4 == 0) && payload <= J.in_bytes && J.pay_off <= J.in_bytes - payload;
+  paydw = payload / 4;
+  t = sizeof(T) == 4 ? (T)t32 : (T)t64;
+  return good;
+}
+
+// Block layout of superblock sb of an incoming stream, read by one wave:
+// its payload range [E, En) in dwords from the payload start and, for
+// segment 64h + lane (h = 0, 1), its block's kind, width, existence and
+// payload offset from E; half0 = the payload dwords of the first 64
+// segments' blocks.
+struct WaveBlocks {
+  uint64_t E, En;
+  uint32_t kind[2], F[2], boff[2], half0;
+  bool ex[2];
+};
+
+// False if the table entries, header bytes or block sizes are inconsistent
+// (the same checks as the strip decoder's).
+template <typename T, int L>
+__device__ bool wave_blocks(const Job& J, const uint8_t* in, uint64_t sb, uint64_t paydw,
+                            uint32_t nval, WaveBlocks& wb) {
+  constexpr uint32_t EW = sizeof(T) / 4, LPB = L / 32, BPS = SUPER / L;
+  const uint32_t lane = __lane_id();
+  const uint32_t* table = (const uint32_t*)(in + HDR);
+  // table words and header bytes are read together (clamped indices, no
+  // conditional loads)
+  const uint32_t ta = table[sb];
+  const uint32_t tb = table[min(sb + 1, J.NS - 1)];
+  const uint64_t b0 = sb * BPS;
+  const uint64_t hb_end = (J.B + 3) & ~3ull;
+  const uint64_t hidx = min(b0 + 4ull * (lane & (BPS / 4 - 1)), hb_end - 4);
+  const uint32_t hraw = *(const uint32_t*)(in + J.hdr_off + hidx);
+  const uint32_t hw = (lane < BPS / 4 && b0 + 4ull * lane < hb_end) ? hraw : 0u;
+  const uint64_t E = ta;
+  const uint64_t En = sb + 1 < J.NS ? (uint64_t)tb : paydw;
+  bool good = (sb != 0 || E == 0) && E <= En && En <= paydw && En - E <= (uint64_t)SUPER * EW;
+  // header bytes past the last block (zero padding of the last word)
+  if (lane < BPS / 4) {
+#pragma unroll
+    for (uint32_t k = 0; k < 4; ++k) {
+      const uint64_t bb = b0 + 4ull * lane + k;
+      if (bb >= J.B && bb < hb_end && ((hw >> (8 * k)) & 0xFFu)) good = false;
+    }
+  }
+  // kinds, widths and sizes of the lane's two blocks; exclusive offsets
+  uint32_t tot = 0;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const uint32_t seg = 64 * h + lane, lb = seg / LPB, w = seg % LPB;
+    const uint32_t hb = (__shfl(hw, (int)(lb / 4)) >> (8 * (lb % 4))) & 0xFFu;
+    const bool ex = lb * (uint32_t)L < nval;
+    const uint32_t m = ex ? min((uint32_t)L, nval - lb * (uint32_t)L) : 0u;
+    const uint32_t kd = ex ? hb >> 5 : 0u, f = ex ? hb & 31u : 0u;
+    uint32_t size_dw = 0;
+    bool hv = true;
+    if (kd == K_ZERO) hv = f == 0;
+    else if (kd == K_RAW) { hv = f == 0; size_dw = m * EW; }
+    else if (kd == K_L1D) size_dw = 1u + (f ? (f + 1u) * LPB : 0u);
+    else hv = false;
+    if (!hv) size_dw = 0;
+    good = good && hv;
+    const uint32_t contrib = w == 0 ? size_dw : 0u;
+    const uint32_t incl = wave_incl_scan(contrib);
+    const uint32_t excl = tot + incl - contrib;
+    wb.boff[h] = w == 0 ? excl : excl - size_dw;  // later lanes of a block contribute 0
+    tot += __shfl(incl, 63);
+    if (h == 0) wb.half0 = tot;
+    wb.kind[h] = kd;
+    wb.F[h] = f;
+    wb.ex[h] = ex;
+  }
+  good = good && (uint64_t)tot == En - E;
+  wb.E = E;
+  wb.En = En;
+  return __ballot(good) == ~0ull;
+}
+
+// Copies P payload dwords from src (global) into dst (LDS, 16-byte aligned),
+// realigned so that every load is a whole 16-byte chunk: only bytes inside
+// [16-byte floor of src, src + P) are read, and src lies past the stream's
+// fixed part.  Returns where src[0] landed (dst + 0..3).  MAXW bounds P.
+template <uint32_t MAXW>
+__device__ __forceinline__ const uint32_t* wave_stage_payload(const uint32_t* src, uint32_t P,
+                                                              uint32_t* dst) {
+  const uint32_t lane = __lane_id();
+  const uint32_t delta = (uint32_t)(((uintptr_t)src & 15u) >> 2);
+  const u4u* al = (const u4u*)(src - delta);
+  const uint32_t full = (delta + P) / 4, nch = (delta + P + 3) / 4;
+  u4u* d4 = (u4u*)dst;
+  constexpr uint32_t MAXCH = (MAXW + 3) / 4 + 1;
+  for (uint32_t k0 = 0; k0 < MAXCH && k0 < full; k0 += 8 * 64) {
+    u4u r[8];
+#pragma unroll
+    for (uint32_t u = 0; u < 8; ++u) r[u] = al[min(k0 + u * 64 + lane, full - 1)];
+#pragma unroll
+    for (uint32_t u = 0; u < 8; ++u)
+      if (k0 + u * 64 + lane < full) d4[k0 + u * 64 + lane] = r[u];
+  }
+  if (full < nch && lane == 0) {
+    const uint32_t* q = (const uint32_t*)(al + full);
+    const uint32_t lim = delta + P - 4 * full;  // 1..3 valid dwords
+    u4u r;
+    r.x = q[0];
+    r.y = lim > 1 ? q[1] : 0u;
+    r.z = lim > 2 ? q[2] : 0u;
+    r.w = 0u;
+    d4[full] = r;
+  }
+  return dst + delta;
+}
+
+// Decodes superblock sb into J.out; false (nothing written) if it is malformed.
+template <typename T, int L>
+__device__ bool wave_decode_super(const Job& J, const uint8_t* in, uint64_t sb, uint64_t paydw,
+                                  T t, uint32_t* R) {
+  constexpr uint32_t EW = sizeof(T) / 4, LPB = L / 32;
+  constexpr uint32_t SEGW = 32 * EW, STR = seg_stride<T>();
+  const uint32_t lane = __lane_id();
+  const uint64_t e0 = sb * SUPER;
+  const uint32_t nval = (uint32_t)min((uint64_t)SUPER, J.n - e0);
+  WaveBlocks wb;
+  if (!wave_blocks<T, L>(J, in, sb, paydw, nval, wb)) return false;
+  const uint32_t* S = wave_stage_payload<SUPER * EW>(
+      (const uint32_t*)(in + J.pay_off) + wb.E, (uint32_t)(wb.En - wb.E), R);
+  wave_lds_sync();
+  const uint32_t* boff = wb.boff;
+  const uint32_t* kind = wb.kind;
+  const uint32_t* F = wb.F;
+  const bool* ex = wb.ex;
+  T v0[32], v1[32];
+  {
+    const uint32_t seg = lane, w = seg % LPB;
+    const uint32_t vc = (uint32_t)min(32, max(0, (int)nval - (int)(seg * 32)));
+    if (nval == SUPER) unpack_seg<T, LPB, true>(S + boff[0], kind[0], F[0], w, vc, ex[0], t, v0);
+    else unpack_seg<T, LPB, false>(S + boff[0], kind[0], F[0], w, vc, ex[0], t, v0);
+  }
+  {
+    const uint32_t seg = 64 + lane, w = seg % LPB;
+    const uint32_t vc = (uint32_t)min(32, max(0, (int)nval - (int)(seg * 32)));
+    if (nval == SUPER) unpack_seg<T, LPB, true>(S + boff[1], kind[1], F[1], w, vc, ex[1], t, v1);
+    else unpack_seg<T, LPB, false>(S + boff[1], kind[1], F[1], w, vc, ex[1], t, v1);
+  }
+  wave_lds_sync();  // every lane has read its payload words
+  // values into the padded segment layout, then coalesced 16-byte stores
+  {
+    uint32_t* p0 = R + lane * STR;
+    uint32_t* p1 = R + (64 + lane) * STR;
+#pragma unroll
+    for (int i = 0; i < 32; ++i) {
+      uint32_t wd[2];
+      raw_words(v0[i], wd);
+      p0[i * EW] = wd[0];
+      if (EW == 2) p0[i * EW + 1] = wd[1];
+      raw_words(v1[i], wd);
+      p1[i * EW] = wd[0];
+      if (EW == 2) p1[i * EW + 1] = wd[1];
+    }
+  }
+  wave_lds_sync();
+  uint32_t* d32 = (uint32_t*)((T*)J.out + e0);
+  const uint32_t vdw = nval * EW;
+  if (nval == SUPER) {
+#pragma unroll
+    for (uint32_t u = 0; u < SUPER * EW / 4 / 64; ++u) {  // 16 (fp32) or 32 (fp64) chunks per lane
+      const uint32_t k = u * 64 + lane, dw = 4 * k;
+      const u4u r = *(const u4u*)(R + (dw / SEGW) * STR + dw % SEGW);
+      ((u4u*)d32)[k] = r;
+    }
+  } else {
+    for (uint32_t k = lane; 4 * k < vdw; k += 64) {
+      const uint32_t dw = 4 * k;
+      const u4u r = *(const u4u*)(R + (dw / SEGW) * STR + dw % SEGW);
+      if (dw + 4 <= vdw) {
+        ((u4u*)d32)[k] = r;
+      } else {
+        if (dw + 0 < vdw) d32[dw + 0] = r.x;
+        if (dw + 1 < vdw) d32[dw + 1] = r.y;
+        if (dw + 2 < vdw) d32[dw + 2] = r.z;
+      }
+    }
+  }
+  wave_lds_sync();  // the region is read before the next superblock's copy-in
+  return true;
+}
+
+template <typename T, int L>
+__global__ __launch_bounds__(WaveDec<T>::WAVES * 64)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1, 2))) void k_decompress_w(Job J, Ctl C) {
+  const uint32_t wid = threadIdx.x >> 6;
+  uint32_t* R = g_stage + wid * WaveDec<T>::REGION;
+  const uint8_t* in = (const uint8_t*)J.in;
+  uint64_t paydw = 0;
+  T t = 0;
+  bool bad = !wave_header<T>(J, in, paydw, t);
+  if (!bad) {
+    const uint64_t W = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    for (uint64_t sb = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wid; sb < J.NS; sb += W)
+      if (!wave_decode_super<T, L>(J, in, sb, paydw, t, R)) bad = true;
+  }
+  if (bad && __lane_id() == 0) atomicOr(&C.ctrl->err, ERRF_CORRUPT);
+}
+
+// ---------------------------------------------------------- per-wave encode
+// fp32 1D encoding (compression and the fused step) by single waves.  A wave
+// claims a superblock, builds its payload in LDS in two halves of 64
+// segments (lane l codes segment 64h + l), learns its offset and writes
+// payload, table word and header bytes.  There is no workgroup barrier, so
+// the waves of a CU are in different phases (loads, arithmetic, waits,
+// stores) at once.  Offsets come from a two-level scan: a workgroup claims
+// rounds of WAVES consecutive superblocks with one global ticket; inside a
+// round the waves combine their sizes through LDS, and the round is one
+// element of the decoupled look-back (a look-back per superblock measured
+// slower than strips: eight times as many chain elements published eight
+// times as fast outrun a 64-word probe within one memory round trip).
+// Wave region (dwords): X, 64 padded segments (input values, the incoming
+// half's payload, the addend, then the second half's payload); A, the first
+// half's payload; HB, the superblock's header bytes.
+struct WaveEnc {
+  static constexpr uint32_t WAVES = 8;  // per workgroup
+  static constexpr uint32_t STR = 36;   // seg_stride<float>()
+  static constexpr uint32_t XW = 64 * STR, AW = 64 * SEG, HBW = SUPER / 32 / 4;
+  static constexpr uint32_t REGION = XW + AW + HBW + 4;
+};
+
+// One half's 2048 values src[0 .. hval) into registers, 16-byte loads, eight
+// per lane in flight (positions past hval read as 0).
+__device__ __forceinline__ void wave_half_load(const uint32_t* src, uint32_t hval, u4u (&r)[8]) {
+  const uint32_t lane = __lane_id();
+  if (hval == 64 * SEG) {
+#pragma unroll
+    for (uint32_t u = 0; u < 8; ++u) r[u] = ((const u4u*)src)[u * 64 + lane];
+    return;
+  }
+#pragma unroll
+  for (uint32_t u = 0; u < 8; ++u) {
+    const uint32_t dw = 4 * (u * 64 + lane);
+    if (dw + 4 <= hval) {
+      r[u] = *(const u4u*)(src + dw);
+    } else {
+      r[u].x = dw + 0 < hval ? src[dw + 0] : 0u;
+      r[u].y = dw + 1 < hval ? src[dw + 1] : 0u;
+      r[u].z = dw + 2 < hval ? src[dw + 2] : 0u;
+      r[u].w = 0u;
+    }
+  }
+}
+
+// Registers of wave_half_load into X's padded segment layout.
+__device__ __forceinline__ void wave_regs_to_x(const u4u (&r)[8], uint32_t* X) {
+  const uint32_t lane = __lane_id();
+#pragma unroll
+  for (uint32_t u = 0; u < 8; ++u) {
+    const uint32_t dw = 4 * (u * 64 + lane);
+    *(u4u*)(X + (dw / SEG) * WaveEnc::STR + dw % SEG) = r[u];
+  }
+}
+
+__device__ __forceinline__ void wave_row_get(const uint32_t* X, float (&v)[32]) {
+  const f4u* p = (const f4u*)(X + __lane_id() * WaveEnc::STR);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const f4u r = p[k];
+    v[4 * k] = r.x; v[4 * k + 1] = r.y; v[4 * k + 2] = r.z; v[4 * k + 3] = r.w;
+  }
+}
+
+__device__ __forceinline__ void wave_row_put(uint32_t* X, const float (&v)[32]) {
+  f4u* p = (f4u*)(X + __lane_id() * WaveEnc::STR);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    f4u r;
+    r.x = v[4 * k]; r.y = v[4 * k + 1]; r.z = v[4 * k + 2]; r.w = v[4 * k + 3];
+    p[k] = r;
+  }
+}
+
+// The lane's share of its block's payload at st (the block's first word):
+// base, sign word and planes of an L1D block, or the values of a RAW block
+// (from registers, re-derived by the fused step, or re-read from J.in).
+template <int L, bool FUSED, bool FULL>
+__device__ __forceinline__ void wave_pack(const Job& J, uint64_t seg, uint32_t w, uint32_t vcnt,
+                                          const LaneCode& lc, const FusedSrc& fs, uint32_t* st) {
+  constexpr uint32_t LPB = L / 32;
+  if (lc.kind == K_L1D) {
+    if (w == 0) st[0] = (uint32_t)lc.base;
+    if (lc.F) {
+      st[1 + w] = lc.sg;
+      put_planes(lc.a, lc.F, st + 1 + LPB + w, LPB);
+    }
+  }
+  if (FUSED && lc.kind == K_RAW && lc.rawregs) {
+#pragma unroll
+    for (int i = 0; i < 32; ++i)  // unrolled: a[] stays in registers
+      if (FULL || i < (int)vcnt) st[w * 32 + i] = lc.a[i];
+  } else if (lc.kind == K_RAW) {  // blocks too wide to code (rare)
+    if (FUSED) {
+      fused_raw_stage<LPB>(J, fs, seg, w, vcnt, st);
+    } else {
+      const float* src = (const float*)J.in + seg * SEG;
+      for (int i = 0; i < (int)vcnt; ++i) st[w * 32 + i] = __float_as_uint(src[i]);
+    }
+  }
+}
+
+// Encodes superblock u of job J (fused: incoming stream J.in plus addend
+// J.local); gs: its look-back word, chain0 the job's first.  nxt: the
+// wave's next ticket, taken once the offset is known.
+// Encodes superblock u of job J into the wave's region (fused: incoming
+// stream J.in plus addend J.local): tot[0] payload dwords in A, tot[1] in X,
+// header bytes in HB; good is false for a malformed incoming superblock.
+template <int L, bool FUSED, bool FULL>
+__device__ __forceinline__ void wave_encode_unit(const Job& J, uint64_t u, uint32_t* R,
+                                                 uint32_t (&tot)[2], bool& good) {
+  constexpr uint32_t LPB = L / 32, BPS = SUPER / L, HALF = 64 * SEG;
+  const uint32_t lane = __lane_id();
+  const uint32_t w = lane & (LPB - 1);
+  uint32_t* X = R;
+  uint32_t* A = R + WaveEnc::XW;
+  uint32_t* HB = A + WaveEnc::AW;
+  const uint64_t e0 = u * SUPER;
+  const uint32_t nval = FULL ? SUPER : (uint32_t)min((uint64_t)SUPER, J.n - e0);
+  const uint8_t* in = (const uint8_t*)J.in;
+  u4u pre[8];  // compression: the input half in flight
+  if (!FUSED)
+    wave_half_load((const uint32_t*)((const float*)J.in + e0),
+                   FULL ? HALF : (uint32_t)min((uint32_t)HALF, nval), pre);
+
+  // the incoming superblock's layout (fused step)
+  good = true;
+  WaveBlocks wb = {};
+  FusedSrc fs;
+  fs.pay = (const uint32_t*)(in + J.pay_off);
+  fs.t = 0.0f;
+  if (FUSED) {
+    uint64_t paydw = 0;
+    good = wave_header<float>(J, in, paydw, fs.t);
+    if (good) good = wave_blocks<float, L>(J, in, u, paydw, nval, wb);
+  }
+
+#pragma unroll
+  for (uint32_t h = 0; h < 2; ++h) {
+    const uint32_t hval =
+        FULL ? HALF : (uint32_t)min((int)HALF, max(0, (int)nval - (int)(h * HALF)));
+    const uint64_t seg = e0 / SEG + 64 * h + lane;
+    const uint32_t vcnt = FULL ? 32u : (uint32_t)min(32, max(0, (int)hval - 32 * (int)lane));
+    float v[32];
+    if (FUSED) {
+      const uint32_t hoff = h ? wb.half0 : 0u;
+      const uint32_t* S = X;
+      if (good) {
+        const uint32_t P = h ? (uint32_t)(wb.En - wb.E) - wb.half0 : wb.half0;
+        S = wave_stage_payload<HALF>(fs.pay + wb.E + hoff, P, X);
+      }
+      // the addend's loads are in flight during the decode
+      u4u lr[8];
+      wave_half_load((const uint32_t*)(J.local + e0 + h * HALF), hval, lr);
+      if (good) {
+        wave_lds_sync();
+        unpack_seg<float, LPB, FULL>(S + (wb.boff[h] - hoff), wb.kind[h], wb.F[h], w, vcnt,
+                                     wb.ex[h], fs.t, v);
+        fs.di.off_dw = (uint32_t)wb.E + wb.boff[h];
+        fs.di.kind = wb.kind[h];
+        fs.di.F = wb.F[h];
+      } else {
+#pragma unroll
+        for (int i = 0; i < 32; ++i) v[i] = 0.0f;
+        fs.di.off_dw = 0;
+        fs.di.kind = K_ZERO;
+        fs.di.F = 0;
+      }
+      wave_lds_sync();  // payload words read before X takes the addend
+      wave_regs_to_x(lr, X);
+      wave_lds_sync();
+      float a[32];
+      wave_row_get(X, a);
+#pragma unroll
+      for (int i = 0; i < 32; ++i) v[i] = v[i] + a[i];  // incoming + local, fp32
+      wave_row_put(X, v);  // the sums, for a RAW block (own row)
+    } else {
+      // the first half's loads were issued by the caller (pre); the second
+      // half's go out as soon as the first half's registers are free
+      wave_regs_to_x(pre, X);
+      wave_lds_sync();
+      wave_row_get(X, v);
+      if (h == 0) {
+        const uint32_t h1 =
+            FULL ? HALF : (uint32_t)min((int)HALF, max(0, (int)nval - (int)HALF));
+        wave_half_load((const uint32_t*)((const float*)J.in + e0 + HALF), h1, pre);
+      }
+    }
+    LaneCode lc;
+    analyze_1d<float, L, FULL, FUSED>(J, seg, w, v, vcnt, lc,
+                                      FUSED ? X + lane * WaveEnc::STR : nullptr);
+    const uint32_t contrib = w == 0 ? lc.size_dw : 0u;
+    const uint32_t incl = wave_incl_scan(contrib);
+    const uint32_t boff = w == 0 ? incl - contrib : incl - lc.size_dw;
+    tot[h] = __shfl(incl, 63);
+    if (w == 0)
+      ((uint8_t*)HB)[(64 * h + lane) / LPB] =
+          (uint8_t)(lc.exists ? ((lc.kind << 5) | lc.F) : 0u);
+    wave_lds_sync();  // every row of X is read before the second half's payload goes there
+    wave_pack<L, FUSED, FULL>(J, seg, w, vcnt, lc, fs, (h ? X : A) + boff);
+  }
+  wave_lds_sync();  // A, X and HB are complete
+}
+
+// Writes superblock u's payload (tot[0] dwords from A, tot[1] from X) at
+// dword offset ex of the job's payload, its table word and header bytes;
+// the job's last superblock also writes the stream header and size.
+template <int L>
+__device__ __forceinline__ void wave_write_unit(const Job& J, uint64_t u, uint64_t ex,
+                                                const uint32_t (&tot)[2], const uint32_t* R) {
+  constexpr uint32_t BPS = SUPER / L;
+  const uint32_t lane = __lane_id();
+  const uint32_t* X = R;
+  const uint32_t* A = R + WaveEnc::XW;
+  const uint32_t* HB = A + WaveEnc::AW;
+  uint8_t* base8 = (uint8_t*)J.out;
+  uint32_t* dst = (uint32_t*)(base8 + J.pay_off) + ex;
+  for (uint32_t k = lane; k < tot[0]; k += 64) dst[k] = A[k];
+  for (uint32_t k = lane; k < tot[1]; k += 64) dst[tot[0] + k] = X[k];
+  if (lane == 0) ((uint32_t*)(base8 + HDR))[u] = (uint32_t)ex;
+  const uint64_t b0 = u * BPS;
+  if (lane < BPS / 4 && b0 + 4 * lane < J.B)
+    *(uint32_t*)(base8 + J.hdr_off + b0 + 4 * lane) = HB[lane];
+  if (u == J.NS - 1 && lane < 16) {
+    const uint64_t payload = 4 * (ex + tot[0] + tot[1]);
+    ((uint32_t*)base8)[lane] = hdr_word(J, lane, payload);
+    if (lane == 0 && J.out_bytes) *J.out_bytes = J.pay_off + payload;
+  }
+  wave_lds_sync();  // the region is read before the next superblock reuses it
+}
+
+// ---- rounds.  A workgroup's waves claim slots of rounds through an LDS
+// counter (claim k: round k / WAVES, slot k % WAVES); the first claimer of
+// a round takes its global ticket T, and slot s of the round is superblock
+// WAVES * (T's round within its job) + s.  Per round (a ring of RING
+// entries in LDS): the slots' sizes, a count of them, and the round's
+// exclusive prefix, fetched by one elected wave with the look-back over
+// rounds.  The wave that completes the count publishes the round's
+// aggregate (or its inclusive prefix, if the prefix is known); the fetcher
+// publishes the inclusive prefix if the count is complete.  Either way the
+// round's status word is published, and an inclusive word is not left
+// overwritten by an aggregate (the completer re-checks for the prefix once
+// its aggregate store has completed).
+// Deadlock freedom: every wait is on earlier rounds (tickets handed to
+// running workgroups) or on earlier slots of the same round (claimed
+// before, by waves of the same workgroup); the first claimer of a round
+// waits for the round RING earlier in the same entry to be released by all
+// its claimers, each of which releases it once.  Nothing assumes that the
+// grid's workgroups are resident together, and every wait is bounded.
+constexpr uint32_t RING = 4;
+constexpr uint32_t SIZE_NONE = 0xFFFFFFFFu;
+
+struct RoundState {
+  unsigned long long prefix;  // exclusive prefix of the round (dwords)
+  uint32_t ticket;
+  uint32_t ready;     // 1 + round number once ticket (and the reset) is done
+  uint32_t cnt;       // sizes written
+  uint32_t fetch;     // 1 once a wave has been elected to fetch the prefix
+  uint32_t pready;    // 1 + round number once prefix is set
+  uint32_t released;  // claimers done with this entry
+  uint32_t size[WaveEnc::WAVES];
+};
+struct WaveSched {
+  uint32_t claim;
+  RoundState rs[RING];
+};
+
+// Clears the schedule (before the workgroup's first barrier).
+__device__ __forceinline__ void wave_sched_init(WaveSched& ws) {
+  if (threadIdx.x == 0) {
+    ws.claim = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < RING; ++i) {
+      ws.rs[i].ready = 0;
+      ws.rs[i].released = WaveEnc::WAVES;
+    }
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ uint32_t lds_load_acq(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_store_rel(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Bounded wait until *p >= want (lane 0 polls); false on timeout.
+__device__ __forceinline__ bool lds_wait_ge(const Ctl& C, const uint32_t* p, uint32_t want) {
+  uint32_t ok = 1;
+  if (__lane_id() == 0) {
+    uint32_t spins = 0;
+    uint64_t t0 = 0;
+    while (lds_load_acq(p) < want) {
+      if (wait_over(C, ++spins, t0)) {
+        atomicOr(&C.ctrl->err, ERRF_TIMEOUT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  return __shfl(ok, 0) != 0;
+}
+
+struct Claim {
+  uint32_t round, slot, ticket;  // ticket 0xFFFFFFFF: timed out
+};
+
+__device__ __forceinline__ Claim wave_claim(const Ctl& C, WaveSched& ws) {
+  const uint32_t lane = __lane_id();
+  uint32_t k = 0;
+  if (lane == 0) k = atomicAdd(&ws.claim, 1u);
+  k = __builtin_amdgcn_readfirstlane(__shfl(k, 0));
+  Claim c;
+  c.round = k / WaveEnc::WAVES;
+  c.slot = k % WaveEnc::WAVES;
+  RoundState& rs = ws.rs[c.round % RING];
+  if (c.slot == 0) {
+    // the entry's previous round has been released by all its claimers
+    if (!lds_wait_ge(C, &rs.released, WaveEnc::WAVES)) {
+      c.ticket = 0xFFFFFFFFu;
+      return c;
+    }
+    uint32_t t = 0;
+    if (lane == 0) {
+      rs.cnt = 0;
+      rs.fetch = 0;
+      rs.pready = 0;
+      rs.released = 0;
+#pragma unroll
+      for (uint32_t i = 0; i < WaveEnc::WAVES; ++i) rs.size[i] = SIZE_NONE;
+      t = atomicAdd(&C.ctrl->ticket, 1u);
+      rs.ticket = t;
+      lds_store_rel(&rs.ready, c.round + 1);
+    }
+    c.ticket = __builtin_amdgcn_readfirstlane(__shfl(t, 0));
+    return c;
+  }
+  if (!lds_wait_ge(C, &rs.ready, c.round + 1)) {
+    c.ticket = 0xFFFFFFFFu;
+    return c;
+  }
+  c.ticket = __builtin_amdgcn_readfirstlane(rs.ticket);
+  return c;
+}
+
+// The claimer is done with its round's entry.
+__device__ __forceinline__ void wave_release(RoundState& rs) {
+  if (__lane_id() == 0)
+    __hip_atomic_fetch_add(&rs.released, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ uint32_t round_sum(const RoundState& rs) {
+  uint32_t a = 0;
+#pragma unroll
+  for (uint32_t i = 0; i < WaveEnc::WAVES; ++i) a += rs.size[i];
+  return a;
+}
+
+// Superblock u (slot cl.slot of round entry rs; u >= J.NS: an empty slot
+// past the job's end) of round gs of the chain that starts at chain0.
+template <int L, bool FUSED>
+__device__ __forceinline__ void wave_round_unit(const Job& J, uint64_t u, const Claim& cl,
+                                                RoundState& rs, uint64_t gs, uint64_t chain0,
+                                                const Ctl& C, uint32_t ep, uint32_t* R) {
+  const uint32_t lane = __lane_id();
+  const bool live = u < J.NS;
+  uint32_t tot[2] = {0u, 0u};
+  bool good = true;
+  if (live) {
+    if ((u + 1) * SUPER <= J.n) wave_encode_unit<L, FUSED, true>(J, u, R, tot, good);
+    else wave_encode_unit<L, FUSED, false>(J, u, R, tot, good);
+  }
+  // the size into the round; the wave completing the count publishes
+  if (lane == 0) {
+    __hip_atomic_store(&rs.size[cl.slot], tot[0] + tot[1], __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_WORKGROUP);
+    const uint32_t c =
+        __hip_atomic_fetch_add(&rs.cnt, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP) + 1;
+    if (c == WaveEnc::WAVES) {
+      const uint32_t agg = round_sum(rs);
+      if (lds_load_acq(&rs.pready) >= cl.round + 1) {
+        st_agent(C.status + gs, sw_pack(2, ep, rs.prefix + agg));
+      } else {
+        publish_agg(C, gs, chain0, ep, agg);
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): that store has completed
+        if (lds_load_acq(&rs.pready) >= cl.round + 1)
+          st_agent(C.status + gs, sw_pack(2, ep, rs.prefix + agg));
+      }
+    }
+  }
+  if (!live) {
+    wave_release(rs);
+    return;
+  }
+  // the round's prefix: fetched by one wave, read by the others
+  uint32_t fetcher = 0;
+  if (lane == 0) fetcher = atomicCAS(&rs.fetch, 0u, 1u) == 0u ? 1u : 0u;
+  fetcher = __shfl(fetcher, 0);
+  bool to = false;
+  uint64_t prefix = 0;
+  if (fetcher) {
+    prefix = lookback<1, false>(C, gs, chain0, ep, 0, to);
+    if (lane == 0) {
+      rs.prefix = prefix;
+      lds_store_rel(&rs.pready, cl.round + 1);
+      if (lds_load_acq(&rs.cnt) == WaveEnc::WAVES && !to)
+        st_agent(C.status + gs, sw_pack(2, ep, prefix + round_sum(rs)));
+    }
+  } else {
+    to = !lds_wait_ge(C, &rs.pready, cl.round + 1);
+    prefix = rs.prefix;
+  }
+  // plus the sizes of the round's earlier slots
+  uint32_t below = 0;
+  if (lane < cl.slot) {
+    uint32_t spins = 0;
+    uint64_t t0 = 0;
+    uint32_t v;
+    while ((v = lds_load_acq(&rs.size[lane])) == SIZE_NONE) {
+      if (wait_over(C, ++spins, t0)) {
+        to = true;
+        v = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    below = v;
+  }
+  to = __ballot(to) != 0;
+  below = (uint32_t)wave_sum64(below);
+  if (lane == 0) {
+    if (to) atomicOr(&C.ctrl->err, ERRF_TIMEOUT);
+    if (!good) atomicOr(&C.ctrl->err, ERRF_CORRUPT);
+  }
+  if (!to && good) wave_write_unit<L>(J, u, prefix + below, tot, R);
+  wave_release(rs);
+}
+
+#define GZ_WAVE_ATTR __launch_bounds__(WaveEnc::WAVES * 64) __attribute__((amdgpu_waves_per_eu(2, 2)))
+// Rounds of a job of NS superblocks.
+__device__ __forceinline__ uint64_t rounds_of(uint64_t NS) {
+  return (NS + WaveEnc::WAVES - 1) / WaveEnc::WAVES;
+}
+
+// One stream: round ticket T covers superblocks WAVES * T + slot, look-back
+// word T.
+template <int L, bool FUSED>
+__global__ GZ_WAVE_ATTR void k_encode_w(Job J, Ctl C) {
+  __shared__ WaveSched ws;
+  wave_sched_init(ws);
+  uint32_t* R = g_stage + (threadIdx.x >> 6) * WaveEnc::REGION;
+  const uint32_t ep = ld_agent32(&C.ctrl->epoch);
+  const uint64_t NR = rounds_of(J.NS);
+  for (;;) {
+    const Claim cl = wave_claim(C, ws);
+    RoundState& rs = ws.rs[cl.round % RING];
+    if (cl.ticket >= NR) {  // past the end (or timed out)
+      wave_release(rs);
+      break;
+    }
+    wave_round_unit<L, FUSED>(J, (uint64_t)cl.ticket * WaveEnc::WAVES + cl.slot, cl, rs,
+                              cl.ticket, 0, C, ep, R);
+  }
+  epilogue(C);
+}
+// njobs streams of NS superblocks each (total = njobs x rounds per job),
+// every one its own chain: round ticket T is round T / njobs of job
+// T % njobs, look-back word j x rounds + round.
+template <int L, bool FUSED>
+__global__ GZ_WAVE_ATTR void k_batch_encode_w(const Job* __restrict__ jobs, uint32_t njobs,
+                                              uint32_t total, Ctl C) {
+  __shared__ WaveSched ws;
+  wave_sched_init(ws);
+  uint32_t* R = g_stage + (threadIdx.x >> 6) * WaveEnc::REGION;
+  const uint32_t ep = ld_agent32(&C.ctrl->epoch);
+  for (;;) {
+    const Claim cl = wave_claim(C, ws);
+    RoundState& rs = ws.rs[cl.round % RING];
+    if (cl.ticket >= total) {  // past the end (or timed out)
+      wave_release(rs);
+      break;
+    }
+    const uint32_t j = cl.ticket % njobs;
+    const Job J = jobs[j];
+    const uint64_t NR = rounds_of(J.NS), r = cl.ticket / njobs;
+    wave_round_unit<L, FUSED>(J, r * WaveEnc::WAVES + cl.slot, cl, rs, j * NR + r, j * NR, C,
+                              ep, R);
+  }
+  epilogue(C);
+}
+
 template <int L, bool FULL>
 __device__ __forceinline__ void fused_body(const Job& J, uint64_t s, uint64_t gs, const Ctl& C,
                                            Smem& sm, uint32_t& tk) {
@@ -1950,6 +2716,68 @@ static hipError_t launch_d(const Job& J, const Ctl& C, uint32_t tpb, uint32_t gr
                      J, C);
   return hipGetLastError();
 }
+template <typename T, int L>
+static hipError_t launch_dw(const Job& J, const Ctl& C, uint32_t grid, hipStream_t st) {
+  const size_t lds = (size_t)WaveDec<T>::WAVES * WaveDec<T>::REGION * 4;
+  hipLaunchKernelGGL((k_decompress_w<T, L>), dim3(grid), dim3(WaveDec<T>::WAVES * 64), lds, st, J,
+                     C);
+  return hipGetLastError();
+}
+
+hipError_t launch_decompress_wave(const Job& J, const Ctl& C, uint32_t cus, hipStream_t st) {
+  const uint32_t waves = J.dtype == 0 ? WaveDec<float>::WAVES : WaveDec<double>::WAVES;
+  const uint64_t need = (J.NS + waves - 1) / waves;
+  const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(cus, need));
+  switch ((J.dtype << 3) | J.log2L) {
+    case 5: return launch_dw<float, 32>(J, C, grid, st);
+    case 6: return launch_dw<float, 64>(J, C, grid, st);
+    case 7: return launch_dw<float, 128>(J, C, grid, st);
+    case 13: return launch_dw<double, 32>(J, C, grid, st);
+    case 14: return launch_dw<double, 64>(J, C, grid, st);
+    case 15: return launch_dw<double, 128>(J, C, grid, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+size_t wave_encode_lds() {
+  return (size_t)WaveEnc::WAVES * WaveEnc::REGION * 4 + sizeof(WaveSched);
+}
+
+template <int L, bool FUSED>
+static hipError_t launch_ew(const Job* d_jobs, const Job& J, uint32_t njobs, uint32_t total,
+                            const Ctl& C, uint32_t cus, hipStream_t st) {
+  // one workgroup per round in flight, at most one per CU (the LDS allows one)
+  const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(cus, total));
+  const size_t lds = (size_t)WaveEnc::WAVES * WaveEnc::REGION * 4;
+  if (d_jobs)
+    hipLaunchKernelGGL((k_batch_encode_w<L, FUSED>), dim3(grid), dim3(WaveEnc::WAVES * 64), lds,
+                       st, d_jobs, njobs, total, C);
+  else
+    hipLaunchKernelGGL((k_encode_w<L, FUSED>), dim3(grid), dim3(WaveEnc::WAVES * 64), lds, st,
+                       J, C);
+  return hipGetLastError();
+}
+
+hipError_t launch_encode_wave(uint32_t op, const Job* d_jobs, const Job& J, uint32_t njobs,
+                              uint32_t total, uint32_t log2L, const Ctl& C, uint32_t cus,
+                              hipStream_t st) {
+  const bool fused = op == 2;
+  switch (log2L) {
+    case 5: return fused ? launch_ew<32, true>(d_jobs, J, njobs, total, C, cus, st)
+                         : launch_ew<32, false>(d_jobs, J, njobs, total, C, cus, st);
+    case 6: return fused ? launch_ew<64, true>(d_jobs, J, njobs, total, C, cus, st)
+                         : launch_ew<64, false>(d_jobs, J, njobs, total, C, cus, st);
+    case 7: return fused ? launch_ew<128, true>(d_jobs, J, njobs, total, C, cus, st)
+                         : launch_ew<128, false>(d_jobs, J, njobs, total, C, cus, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+size_t wave_decode_lds(uint32_t dtype) {
+  return dtype == 0 ? (size_t)WaveDec<float>::WAVES * WaveDec<float>::REGION * 4
+                    : (size_t)WaveDec<double>::WAVES * WaveDec<double>::REGION * 4;
+}
+
 template <int L>
 static hipError_t launch_a(const Job& J, const Ctl& C, uint32_t tpb, uint32_t grid,
                            hipStream_t st) {

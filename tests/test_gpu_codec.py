@@ -52,13 +52,14 @@ def assert_ok(ctx):
 
 def unless_unsupported(fn, dt, tpb):
     """fn() or None where the library reports GZ_EUNSUPPORTED for an fp64
-    workgroup size: 1024 threads are built for fp32 only, and 512 fp64
-    threads may need more LDS than the device gives one workgroup."""
+    workgroup size: 1024 threads are built for fp32 only, 512 fp64 threads
+    may need more LDS than the device gives one workgroup, and the per-wave
+    encoder (threads 64) is fp32 only."""
     from paper_2308_05199_amd import gzccl
     try:
         return fn()
     except gzccl.GzError as e:
-        if e.status == gzccl.GZ_EUNSUPPORTED and dt == np.float64 and tpb >= 512:
+        if e.status == gzccl.GZ_EUNSUPPORTED and dt == np.float64 and (tpb >= 512 or tpb == 64):
             return None
         raise
 
@@ -68,7 +69,7 @@ CASES = [(np.float32, 32), (np.float32, 64), (np.float32, 128),
 
 
 @pytest.mark.parametrize("dt,L", CASES)
-@pytest.mark.parametrize("tpb", [128, 256, 512, 1024])
+@pytest.mark.parametrize("tpb", [0, 64, 128, 256, 512, 1024])   # 0 default, 64 per-wave
 def test_compress_matches_oracle(ctx, oracle, dt, L, tpb):
     say("compress", dt.__name__, L, tpb)
     g = np.random.default_rng(0)
@@ -78,7 +79,7 @@ def test_compress_matches_oracle(ctx, oracle, dt, L, tpb):
     for eb in (1e-4, 3e-6):
         got = unless_unsupported(lambda: gpu_stream(ctx, x, eb, block_len=L, threads=tpb), dt, tpb)
         if got is None:
-            pytest.skip(f"{tpb}-thread fp64 workgroups are not supported on this device")
+            pytest.skip(f"{tpb}-thread fp64 encoding is not built or does not fit this device")
         want = oracle.compress(x, eb, block_len=L)
         assert got.tobytes() == want.tobytes()
     assert_ok(ctx)
@@ -99,7 +100,7 @@ def test_bytes_independent_of_launch_shape(ctx, oracle, grid):
     say("grid", grid)
     x = synth.sinusoids(200_000, seed=2)
     want = oracle.compress(x, 1e-4, block_len=64)
-    for tpb in (128, 256, 512, 1024):
+    for tpb in (64, 128, 256, 512, 1024):
         got = gpu_stream(ctx, x, 1e-4, block_len=64, threads=tpb, grid=grid)
         assert got.tobytes() == want.tobytes()
     assert_ok(ctx)
@@ -111,7 +112,7 @@ def test_small_and_ragged(ctx, oracle, n):
     x = synth.sinusoids(max(n, 1), seed=3)[:n]
     for L in (32, 128):
         want = oracle.compress(x, 1e-4, block_len=L)
-        for tpb in (128, 1024):
+        for tpb in (0, 64, 128, 1024):
             got = gpu_stream(ctx, x, 1e-4, block_len=L, threads=tpb)
             assert got.tobytes() == want.tobytes(), tpb
     assert_ok(ctx)
@@ -130,9 +131,10 @@ def test_special_values(ctx, oracle):
     t = np.float32(2 * 2.0 ** -14)
     x[:5000] = ((np.arange(5000) - 2500 + 0.5) * t).astype(np.float32)
     for eb in (2.0 ** -14, 1e-3, 1e-40):
-        got = gpu_stream(ctx, x, eb)
         want = oracle.compress(x, eb)
-        assert got.tobytes() == want.tobytes()
+        for tpb in (64, 1024):
+            got = gpu_stream(ctx, x, eb, threads=tpb)
+            assert got.tobytes() == want.tobytes(), tpb
     assert_ok(ctx)
 
 
@@ -147,7 +149,7 @@ def test_decompress_matches_oracle(ctx, oracle, dt, L):
     x[17] = np.nan
     s = oracle.compress(x, 1e-4, block_len=L)
     want = oracle.decompress(s)
-    for tpb in (128, 256, 512, 1024):
+    for tpb in (0, 128, 256, 512, 1024):   # 0: the per-wave decoder
         y = unless_unsupported(lambda: ctx.decompress(
             dev(s), n, dtype=torch.float32 if dt == np.float32 else torch.float64, block_len=L,
             threads=tpb), dt, tpb)
@@ -184,11 +186,11 @@ def test_fused_matches_oracle(ctx, oracle, L):
     eb = 1e-4
     s = oracle.compress(a, eb, block_len=L)
     want = oracle.fused_step(s, b, eb, block_len=L)
-    for tpb in (128, 256, 512, 1024):
+    for tpb in (0, 64, 128, 256, 512, 1024):
         out, nb = ctx.fused_reduce_step(dev(s), dev(b), eb, block_len=L, threads=tpb)
         torch.cuda.synchronize()
         got = out[:int(nb.item())].cpu().numpy()
-        assert got.tobytes() == want.tobytes()
+        assert got.tobytes() == want.tobytes(), tpb
     assert_ok(ctx)
 
 
@@ -318,13 +320,12 @@ def test_plan_and_graph_replays(ctx, oracle, gz):
     assert_ok(ctx)
 
 
-@pytest.mark.parametrize("corrupt", ["magic", "n", "reserved_kind", "table", "payload_total",
-                                     "truncated", "pad"])
-def test_corrupt_stream_sets_status(ctx, oracle, corrupt):
-    import torch
-    say("corrupt", corrupt)
-    n = 20_000
-    x = synth.sinusoids(n, seed=30)
+CORRUPTIONS = ["magic", "n", "reserved_kind", "table", "payload_total", "truncated", "pad"]
+
+
+def _corrupt(oracle, corrupt, n, seed):
+    """A stream of n elements with one defect; returns (stream, readable bytes)."""
+    x = synth.sinusoids(n, seed=seed)
     s = oracle.compress(x, 1e-4).copy()
     NS = -(-n // 4096)
     hoff = 64 + 4 * NS
@@ -347,9 +348,19 @@ def test_corrupt_stream_sets_status(ctx, oracle, corrupt):
     if corrupt != "n":  # a different n can still be a well-formed stream
         st, _ = oracle.decompress_status(s[:ib])
         assert st == oracle.ECORRUPT
-    ctx.decompress(dev(s), n, in_bytes=ib)
+    return x, s, ib
+
+
+@pytest.mark.parametrize("corrupt", CORRUPTIONS)
+@pytest.mark.parametrize("tpb", [0, 512])   # per-wave and strip decoders
+def test_corrupt_stream_sets_status(ctx, oracle, corrupt, tpb):
+    import torch
+    say("corrupt", corrupt, tpb)
+    n = 20_000
+    x, s, ib = _corrupt(oracle, corrupt, n, 30)
+    ctx.decompress(dev(s), n, in_bytes=ib, threads=tpb)
     assert ctx.device_status() == 3  # GZ_ECORRUPT, then cleared
-    y = ctx.decompress(dev(oracle.compress(x, 1e-4)), n)
+    y = ctx.decompress(dev(oracle.compress(x, 1e-4)), n, threads=tpb)
     torch.cuda.synchronize()
     assert ctx.device_status() == 0
     assert y.cpu().numpy().tobytes() == oracle.decompress(oracle.compress(x, 1e-4)).tobytes()
@@ -376,6 +387,14 @@ def test_argument_errors(ctx, gz):
     # 1024-thread workgroups are built for fp32 1D kernels only
     with pytest.raises(gz.GzError) as e:
         ctx.compress(torch.zeros(100, dtype=torch.float64, device="cuda"), 1e-3, threads=1024)
+    assert e.value.status == gz.GZ_EUNSUPPORTED
+    # the per-wave kernels (threads 64): no fp64 encoder, no accumulate
+    with pytest.raises(gz.GzError) as e:
+        ctx.compress(torch.zeros(100, dtype=torch.float64, device="cuda"), 1e-3, threads=64)
+    assert e.value.status == gz.GZ_EUNSUPPORTED
+    s64, nb64 = ctx.compress(x, 1e-3)
+    with pytest.raises(gz.GzError) as e:
+        ctx.decompress_add(s64, torch.zeros(100, device="cuda"), threads=64)
     assert e.value.status == gz.GZ_EUNSUPPORTED
     xt = torch.zeros(64 * 64, device="cuda")
     cap = gz.bound(xt.numel(), gz.GZ_F32, 64)
@@ -433,7 +452,7 @@ def test_decompress_dense_payloads(ctx, oracle, dt, kind):
     least = {"dense": 0.6 if dt == np.float32 else 0.4, "raw": 0.99}[kind]
     assert s.size > least * x.nbytes
     tdt = torch.float32 if dt == np.float32 else torch.float64
-    for tpb in (128, 256, 512, 1024):
+    for tpb in (0, 128, 256, 512, 1024):   # 0: the per-wave decoder
         say("  threads", tpb)
         y = unless_unsupported(lambda: ctx.decompress(dev(s), n, dtype=tdt, threads=tpb), dt, tpb)
         if y is None:
@@ -445,4 +464,104 @@ def test_decompress_dense_payloads(ctx, oracle, dt, kind):
             ctx.decompress_add(dev(s), acc, threads=tpb)
             torch.cuda.synchronize()
             assert acc.cpu().numpy().tobytes() == (want + np.float32(1)).tobytes()
+    assert_ok(ctx)
+
+
+@pytest.mark.parametrize("dt,L", CASES)
+def test_wave_decoder_sizes(ctx, oracle, dt, L):
+    """The default decoder (one wave per 4096-element superblock, assigned
+    statically): single elements, one partial superblock, exact superblock
+    multiples, a ragged last superblock, and enough superblocks that every
+    wave decodes several; mixed smooth, NaN, constant, zero and raw-coded
+    blocks.  Decoded values equal the oracle's bit for bit."""
+    import torch
+    g = np.random.default_rng(77)
+    tdt = torch.float32 if dt == np.float32 else torch.float64
+    for n in (1, 33, 4095, 4096, 4097, 70001, (1 << 23) + 12345):
+        say("wave decoder", dt.__name__, L, n)
+        x = synth.sinusoids(n, seed=n % 97).astype(dt)
+        if n > 5000:
+            x[100:4300] = 0
+            x[5000:5200] = dt(3.5e-3)
+            x[4444] = np.nan
+            x[-700:] = g.uniform(500, 1000, 700).astype(dt)
+        s = oracle.compress(x, 1e-4, block_len=L)
+        y = ctx.decompress(dev(s), n, dtype=tdt, block_len=L)
+        torch.cuda.synchronize()
+        assert y.cpu().numpy().view(np.uint8).tobytes() == \
+            oracle.decompress(s).view(np.uint8).tobytes(), n
+    assert_ok(ctx)
+
+
+def _uniform_batch(gz, ns, eb, L, seed):
+    """fp32 compress requests whose lengths share a superblock count."""
+    import torch
+    xs = [synth.sinusoids(n, seed=seed + i) for i, n in enumerate(ns)]
+    cap = max(gz.bound(n, gz.GZ_F32, L) for n in ns)
+    outs = [torch.zeros(cap, dtype=torch.uint8, device="cuda") for _ in ns]
+    nbs = [torch.zeros(1, dtype=torch.int64, device="cuda") for _ in ns]
+    ins = [dev(x) for x in xs]
+    items = [dict(**{"in": i}, out=o, out_bytes=b, n=n, out_cap=cap, eb=eb, dtype=gz.GZ_F32,
+                  block_len=L) for i, o, b, n in zip(ins, outs, nbs, ns)]
+    return xs, ins, outs, nbs, items, cap
+
+
+@pytest.mark.parametrize("L", [32, 64, 128])
+def test_wave_batches_match_oracle(ctx, oracle, gz, L):
+    """Batches the per-wave encoder takes (fp32, one block length, equal
+    superblock counts; here 9 superblocks, full and ragged last ones):
+    compression, then the fused step on its output, by default, with
+    threads 64 and on 1024-thread strips, every stream bitwise the oracle's;
+    a mixed batch asked for waves is refused."""
+    import torch
+    ns = [9 * 4096, 9 * 4096 - 1, 8 * 4096 + 1, 8 * 4096 + 2049]
+    eb = 1e-4
+    xs, ins, outs, nbs, items, cap = _uniform_batch(gz, ns, eb, L, 40)
+    want = [oracle.compress(x, eb, block_len=L) for x in xs]
+    g = np.random.default_rng(41)
+    locs = [g.normal(0, 0.3, n).astype(np.float32) for n in ns]
+    want_f = [oracle.fused_step(w, l, eb, block_len=L) for w, l in zip(want, locs)]
+    for tpb in (0, 64, 1024):
+        say("wave batch", L, tpb)
+        for o in outs:
+            o.zero_()
+        ctx.batch(gz.GZ_OP_COMPRESS, ctx.requests(items), threads=tpb)
+        torch.cuda.synchronize()
+        for w, o, b in zip(want, outs, nbs):
+            assert o[:int(b.item())].cpu().numpy().tobytes() == w.tobytes(), tpb
+        fo = [torch.zeros(cap, dtype=torch.uint8, device="cuda") for _ in ns]
+        fb = [torch.zeros(1, dtype=torch.int64, device="cuda") for _ in ns]
+        fitems = [dict(**{"in": o}, local=dev(l), out=f, out_bytes=b, n=n,
+                       in_bytes=int(nb.item()), out_cap=cap, eb=eb, dtype=gz.GZ_F32,
+                       block_len=L)
+                  for o, l, f, b, n, nb in zip(outs, locs, fo, fb, ns, nbs)]
+        ctx.batch(gz.GZ_OP_FUSED, ctx.requests(fitems), threads=tpb)
+        torch.cuda.synchronize()
+        for w, f, b in zip(want_f, fo, fb):
+            assert f[:int(b.item())].cpu().numpy().tobytes() == w.tobytes(), tpb
+    assert_ok(ctx)
+    mixed = dict(items[0])
+    mixed["n"] = 3 * 4096
+    with pytest.raises(gz.GzError) as e:
+        ctx.batch(gz.GZ_OP_COMPRESS, ctx.requests([items[1], mixed]), threads=64)
+    assert e.value.status == gz.GZ_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("corrupt", CORRUPTIONS)
+@pytest.mark.parametrize("tpb", [0, 1024])   # per-wave and strip kernels
+def test_fused_corrupt_stream_sets_status(ctx, oracle, gz, corrupt, tpb):
+    """A fused step fed a corrupt stream reports GZ_ECORRUPT, and the next
+    valid call is clean and bitwise the oracle's."""
+    import torch
+    say("fused corrupt", corrupt, tpb)
+    n = 20_000
+    x, s, ib = _corrupt(oracle, corrupt, n, 31)
+    loc = np.random.default_rng(32).normal(0, 0.1, n).astype(np.float32)
+    ctx.fused_reduce_step(dev(s), dev(loc), 1e-4, in_bytes=ib, threads=tpb)
+    assert ctx.device_status() == gz.GZ_ECORRUPT
+    s = oracle.compress(x, 1e-4)
+    out, nb = ctx.fused_reduce_step(dev(s), dev(loc), 1e-4, threads=tpb)
+    torch.cuda.synchronize()
+    assert out[:int(nb.item())].cpu().numpy().tobytes() == \
+        oracle.fused_step(s, loc, 1e-4).tobytes()
     assert_ok(ctx)
