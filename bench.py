@@ -645,7 +645,8 @@ def main():
         "headline_1GiB": head,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
-                     "kernel": "k_batch (fused decode-add-encode, 8 chunks per launch)",
+                     "kernel": "k_batch_encode_w<32, true> (per-wave fused decode-add-encode, "
+                               "8 chunks per launch)",
                      "alg_bytes_per_launch": fused_alg,
                      "traffic": traffic},
         "cpu_baseline": cpu,

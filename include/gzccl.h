@@ -78,8 +78,8 @@ typedef struct gz_graph gz_graph;
  * the bytes.  threads 64 selects the per-wave kernels, in which each wave
  * codes whole 4096-element superblocks on its own (grid ignored): 1D
  * decompression of either type, fp32 1D compression and the fused step;
- * GZ_EUNSUPPORTED elsewhere.  They are also the default for those calls
- * when no shape is given or tuned.  mode 0 = 1D blocks, 1 = 8x8 tiles (block_len 64,
+ * GZ_EUNSUPPORTED elsewhere.  With no shape given or tuned, decompression
+ * and the fused step take them, compression takes strips.  mode 0 = 1D blocks, 1 = 8x8 tiles (block_len 64,
  * nx = row length, multiple of 8, n a multiple of 8*nx); select (mode 1):
  * 0 = int8 MLP selector, 1 = exhaustive trial, 2 = always L1D. */
 typedef struct {
@@ -231,9 +231,9 @@ gz_status gz_scatter_decompress(gz_ctx* ctx, const void* d_packed,
  * decode-and-accumulate (fp32 only, as gz_decompress_add); p gives
  * threads/grid only (0: the shapes gz_tune_batch stored for this op and
  * element-type mix, else defaults).  A compress or fused batch whose jobs
- * are all fp32 with the same block length and superblock count runs on the
- * per-wave kernels by default (threads 64; refused with GZ_EUNSUPPORTED for
- * other batches). */
+ * are all fp32 with the same block length and superblock count can run on
+ * the per-wave kernels (threads 64; refused with GZ_EUNSUPPORTED for other
+ * batches); a fused batch does by default. */
 gz_status gz_batch(gz_ctx* ctx, gz_op op, const gz_request* h_reqs,
                    uint32_t nreq, const gz_params* p, gz_stream_t stream);
 

@@ -257,13 +257,18 @@ bool wave_fits(const gz_ctx* c, uint32_t op, uint32_t dt) {
   return (op == 0 || op == 2) && dt == GZ_F32 && gzk::wave_encode_lds() <= c->lds_max;
 }
 
+// Measured defaults: the per-wave kernels for decoding and the fused step,
+// strips for compression (faster there: four waves per SIMD hide the input
+// loads, where the per-wave encoder has two).
+bool wave_default(uint32_t op) { return op == 1 || op == 2; }
+
 // Whether a single 1D call takes the per-wave kernel: asked for (threads
 // 64), tuned, or by default (no threads, grid or tuned shape).
 bool wave_wanted(const gz_ctx* c, uint32_t op, uint32_t dt, uint32_t L, const gz_params* p) {
   if (p && p->threads) return p->threads == WAVE_TPB;
   if (p && p->grid) return false;
   const Tuned& t = c->tuned[tune_op(op)][dt][log2_of(L) - 5];
-  return t.tpb ? t.tpb == WAVE_TPB : true;
+  return t.tpb ? t.tpb == WAVE_TPB : wave_default(op);
 }
 
 gz_status hip_status(hipError_t e) { return e == hipSuccess ? GZ_OK : GZ_EHIP; }
@@ -404,7 +409,7 @@ bool batch_wave_wanted(const gz_ctx* c, gz_op op, const gz_params* p) {
   if (p && p->threads) return p->threads == WAVE_TPB;
   if (p && p->grid) return false;
   const Tuned& t = c->batch_tuned[op][0];
-  return t.tpb ? t.tpb == WAVE_TPB : true;
+  return t.tpb ? t.tpb == WAVE_TPB : wave_default(op);
 }
 
 uint32_t batch_grid(const gz_ctx* c, gz_op op, bool wide, uint32_t tpb, uint64_t total,

@@ -1695,22 +1695,44 @@ struct WaveBlocks {
   bool ex[2];
 };
 
+// The words wave_blocks_eval needs (table entries of sb and sb + 1, the
+// lane's word of header bytes), read together.  SPEC: the stream header
+// has not been checked yet, so offsets are clamped to the readable bytes
+// (a stream that fails the check never has these words used); otherwise
+// the checked header puts them inside the stream.
+template <int L, bool SPEC>
+__device__ __forceinline__ void wave_blocks_load(const Job& J, const uint8_t* in, uint64_t sb,
+                                                 uint32_t (&raw)[3]) {
+  constexpr uint32_t BPS = SUPER / L;
+  const uint32_t lane = __lane_id();
+  const uint64_t hb_end = (J.B + 3) & ~3ull;
+  const uint64_t hidx = min(sb * BPS + 4ull * (lane & (BPS / 4 - 1)), hb_end - 4);
+  const uint64_t o[3] = {HDR + 4 * sb, HDR + 4 * min(sb + 1, J.NS - 1), J.hdr_off + hidx};
+  if (!SPEC) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) raw[i] = *(const uint32_t*)(in + o[i]);
+    return;
+  }
+  if (J.in_bytes < 4) {  // nothing readable (the header check fails too)
+    raw[0] = raw[1] = raw[2] = 0u;
+    return;
+  }
+  const uint64_t lim = (J.in_bytes - 4) & ~3ull;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) raw[i] = *(const uint32_t*)(in + min(o[i], lim));
+}
+
 // False if the table entries, header bytes or block sizes are inconsistent
-// (the same checks as the strip decoder's).
+// (the same checks as the strip decoder's); raw from wave_blocks_load, of a
+// stream whose header passed.
 template <typename T, int L>
-__device__ bool wave_blocks(const Job& J, const uint8_t* in, uint64_t sb, uint64_t paydw,
-                            uint32_t nval, WaveBlocks& wb) {
+__device__ bool wave_blocks_eval(const Job& J, uint64_t sb, uint64_t paydw, uint32_t nval,
+                                 const uint32_t (&raw)[3], WaveBlocks& wb) {
   constexpr uint32_t EW = sizeof(T) / 4, LPB = L / 32, BPS = SUPER / L;
   const uint32_t lane = __lane_id();
-  const uint32_t* table = (const uint32_t*)(in + HDR);
-  // table words and header bytes are read together (clamped indices, no
-  // conditional loads)
-  const uint32_t ta = table[sb];
-  const uint32_t tb = table[min(sb + 1, J.NS - 1)];
+  const uint32_t ta = raw[0], tb = raw[1], hraw = raw[2];
   const uint64_t b0 = sb * BPS;
   const uint64_t hb_end = (J.B + 3) & ~3ull;
-  const uint64_t hidx = min(b0 + 4ull * (lane & (BPS / 4 - 1)), hb_end - 4);
-  const uint32_t hraw = *(const uint32_t*)(in + J.hdr_off + hidx);
   const uint32_t hw = (lane < BPS / 4 && b0 + 4ull * lane < hb_end) ? hraw : 0u;
   const uint64_t E = ta;
   const uint64_t En = sb + 1 < J.NS ? (uint64_t)tb : paydw;
@@ -1754,6 +1776,14 @@ __device__ bool wave_blocks(const Job& J, const uint8_t* in, uint64_t sb, uint64
   wb.E = E;
   wb.En = En;
   return __ballot(good) == ~0ull;
+}
+
+template <typename T, int L>
+__device__ __forceinline__ bool wave_blocks(const Job& J, const uint8_t* in, uint64_t sb,
+                                            uint64_t paydw, uint32_t nval, WaveBlocks& wb) {
+  uint32_t raw[3];
+  wave_blocks_load<L, false>(J, in, sb, raw);
+  return wave_blocks_eval<T, L>(J, sb, paydw, nval, raw, wb);
 }
 
 // Copies P payload dwords from src (global) into dst (LDS, 16-byte aligned),
@@ -1893,13 +1923,15 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1, 2))) void k_decompres
 // element of the decoupled look-back (a look-back per superblock measured
 // slower than strips: eight times as many chain elements published eight
 // times as fast outrun a 64-word probe within one memory round trip).
-// Wave region (dwords): X, 64 padded segments (input values, the incoming
-// half's payload, the addend, then the second half's payload); A, the first
-// half's payload; HB, the superblock's header bytes.
+// Wave region (dwords): X and A, each 64 padded segments, and HB, the
+// superblock's header bytes.  Compression: input values through X, first
+// half's payload in A, second half's in X.  Fused step: the incoming payload
+// staged in X (whole, or half by half if it does not fit), the first half's
+// addend and then payload in A, the second half's addend and payload in X.
 struct WaveEnc {
   static constexpr uint32_t WAVES = 8;  // per workgroup
   static constexpr uint32_t STR = 36;   // seg_stride<float>()
-  static constexpr uint32_t XW = 64 * STR, AW = 64 * SEG, HBW = SUPER / 32 / 4;
+  static constexpr uint32_t XW = 64 * STR, AW = 64 * STR, HBW = SUPER / 32 / 4;
   static constexpr uint32_t REGION = XW + AW + HBW + 4;
 };
 
@@ -2014,9 +2046,16 @@ __device__ __forceinline__ void wave_encode_unit(const Job& J, uint64_t u, uint3
   fs.t = 0.0f;
   if (FUSED) {
     uint64_t paydw = 0;
+    uint32_t raw[3];
+    wave_blocks_load<L, true>(J, in, u, raw);  // in flight with the header's words
     good = wave_header<float>(J, in, paydw, fs.t);
-    if (good) good = wave_blocks<float, L>(J, in, u, paydw, nval, wb);
+    if (good) good = wave_blocks_eval<float, L>(J, u, paydw, nval, raw, wb);
   }
+  // the whole incoming payload is staged at once when its realigned copy
+  // fits X (always, at any ratio above about 1.8)
+  const uint32_t Ptot = good ? (uint32_t)(wb.En - wb.E) : 0u;
+  const bool whole = FUSED && Ptot + 8 <= WaveEnc::XW;
+  const uint32_t* S = X;
 
 #pragma unroll
   for (uint32_t h = 0; h < 2; ++h) {
@@ -2026,11 +2065,11 @@ __device__ __forceinline__ void wave_encode_unit(const Job& J, uint64_t u, uint3
     const uint32_t vcnt = FULL ? 32u : (uint32_t)min(32, max(0, (int)hval - 32 * (int)lane));
     float v[32];
     if (FUSED) {
-      const uint32_t hoff = h ? wb.half0 : 0u;
-      const uint32_t* S = X;
-      if (good) {
-        const uint32_t P = h ? (uint32_t)(wb.En - wb.E) - wb.half0 : wb.half0;
-        S = wave_stage_payload<HALF>(fs.pay + wb.E + hoff, P, X);
+      uint32_t* AD = h ? X : A;  // the addend's transpose, then the sums
+      const uint32_t hoff = (h && !whole) ? wb.half0 : 0u;
+      if (good && (h == 0 || !whole)) {
+        const uint32_t P = whole ? Ptot : (h ? Ptot - wb.half0 : wb.half0);
+        S = wave_stage_payload<SUPER>(fs.pay + wb.E + hoff, P, X);
       }
       // the addend's loads are in flight during the decode
       u4u lr[8];
@@ -2049,14 +2088,14 @@ __device__ __forceinline__ void wave_encode_unit(const Job& J, uint64_t u, uint3
         fs.di.kind = K_ZERO;
         fs.di.F = 0;
       }
-      wave_lds_sync();  // payload words read before X takes the addend
-      wave_regs_to_x(lr, X);
+      wave_lds_sync();  // payload words read before X takes the second addend
+      wave_regs_to_x(lr, AD);
       wave_lds_sync();
       float a[32];
-      wave_row_get(X, a);
+      wave_row_get(AD, a);
 #pragma unroll
       for (int i = 0; i < 32; ++i) v[i] = v[i] + a[i];  // incoming + local, fp32
-      wave_row_put(X, v);  // the sums, for a RAW block (own row)
+      wave_row_put(AD, v);  // the sums, for a RAW block (own row)
     } else {
       // the first half's loads were issued by the caller (pre); the second
       // half's go out as soon as the first half's registers are free
@@ -2071,7 +2110,7 @@ __device__ __forceinline__ void wave_encode_unit(const Job& J, uint64_t u, uint3
     }
     LaneCode lc;
     analyze_1d<float, L, FULL, FUSED>(J, seg, w, v, vcnt, lc,
-                                      FUSED ? X + lane * WaveEnc::STR : nullptr);
+                                      FUSED ? (h ? X : A) + lane * WaveEnc::STR : nullptr);
     const uint32_t contrib = w == 0 ? lc.size_dw : 0u;
     const uint32_t incl = wave_incl_scan(contrib);
     const uint32_t boff = w == 0 ? incl - contrib : incl - lc.size_dw;
