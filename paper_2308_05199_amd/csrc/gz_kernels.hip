@@ -2152,9 +2152,13 @@ __device__ __forceinline__ void wave_write_unit(const Job& J, uint64_t u, uint64
 }
 
 // ---- rounds.  A workgroup's waves claim slots of rounds through an LDS
-// counter (claim k: round k / WAVES, slot k % WAVES); the first claimer of
-// a round takes its global ticket T, and slot s of the round is superblock
-// WAVES * (T's round within its job) + s.  Per round (a ring of RING
+// counter (claim k: round k / WAVES, slot k % WAVES).  A round's global
+// ticket T is taken by the wave that fetched the previous round's prefix,
+// right after: the previous round's waves are then about to write and
+// claim again, so the ticket is held for about one write-out and the
+// round's first claimer need not wait for the atomic (a round past the end
+// hands on a ticket past the end; round 0's first claimer takes its own).
+// Slot s of the round is superblock WAVES * (T's round within its job) + s.  Per round (a ring of RING
 // entries in LDS): the slots' sizes, a count of them, and the round's
 // exclusive prefix, fetched by one elected wave with the look-back over
 // rounds.  The wave that completes the count publishes the round's
@@ -2174,6 +2178,8 @@ constexpr uint32_t SIZE_NONE = 0xFFFFFFFFu;
 
 struct RoundState {
   unsigned long long prefix;  // exclusive prefix of the round (dwords)
+  uint32_t pticket;   // this entry's next round's ticket, taken ahead ...
+  uint32_t pflag;     // ... by the previous round: 1 + the round it is for
   uint32_t ticket;
   uint32_t ready;     // 1 + round number once ticket (and the reset) is done
   uint32_t cnt;       // sizes written
@@ -2194,6 +2200,7 @@ __device__ __forceinline__ void wave_sched_init(WaveSched& ws) {
 #pragma unroll
     for (uint32_t i = 0; i < RING; ++i) {
       ws.rs[i].ready = 0;
+      ws.rs[i].pflag = 0;
       ws.rs[i].released = WaveEnc::WAVES;
     }
   }
@@ -2244,6 +2251,11 @@ __device__ __forceinline__ Claim wave_claim(const Ctl& C, WaveSched& ws) {
       c.ticket = 0xFFFFFFFFu;
       return c;
     }
+    // the round's ticket, handed on by the previous round
+    if (c.round > 0 && !lds_wait_ge(C, &rs.pflag, c.round + 1)) {
+      c.ticket = 0xFFFFFFFFu;
+      return c;
+    }
     uint32_t t = 0;
     if (lane == 0) {
       rs.cnt = 0;
@@ -2252,7 +2264,7 @@ __device__ __forceinline__ Claim wave_claim(const Ctl& C, WaveSched& ws) {
       rs.released = 0;
 #pragma unroll
       for (uint32_t i = 0; i < WaveEnc::WAVES; ++i) rs.size[i] = SIZE_NONE;
-      t = atomicAdd(&C.ctrl->ticket, 1u);
+      t = c.round > 0 ? rs.pticket : atomicAdd(&C.ctrl->ticket, 1u);
       rs.ticket = t;
       lds_store_rel(&rs.ready, c.round + 1);
     }
@@ -2265,6 +2277,14 @@ __device__ __forceinline__ Claim wave_claim(const Ctl& C, WaveSched& ws) {
   }
   c.ticket = __builtin_amdgcn_readfirstlane(rs.ticket);
   return c;
+}
+
+// Hands round r + 1 its ticket (lane 0): a fresh one, or t past the end.
+__device__ __forceinline__ void wave_hand_on(const Ctl& C, WaveSched& ws, uint32_t r,
+                                             uint32_t t, bool fresh) {
+  RoundState& nx = ws.rs[(r + 1) % RING];
+  nx.pticket = fresh ? atomicAdd(&C.ctrl->ticket, 1u) : t;
+  lds_store_rel(&nx.pflag, r + 2);
 }
 
 // The claimer is done with its round's entry.
@@ -2284,8 +2304,9 @@ __device__ __forceinline__ uint32_t round_sum(const RoundState& rs) {
 // past the job's end) of round gs of the chain that starts at chain0.
 template <int L, bool FUSED>
 __device__ __forceinline__ void wave_round_unit(const Job& J, uint64_t u, const Claim& cl,
-                                                RoundState& rs, uint64_t gs, uint64_t chain0,
+                                                WaveSched& ws, uint64_t gs, uint64_t chain0,
                                                 const Ctl& C, uint32_t ep, uint32_t* R) {
+  RoundState& rs = ws.rs[cl.round % RING];
   const uint32_t lane = __lane_id();
   const bool live = u < J.NS;
   uint32_t tot[2] = {0u, 0u};
@@ -2329,6 +2350,7 @@ __device__ __forceinline__ void wave_round_unit(const Job& J, uint64_t u, const 
       lds_store_rel(&rs.pready, cl.round + 1);
       if (lds_load_acq(&rs.cnt) == WaveEnc::WAVES && !to)
         st_agent(C.status + gs, sw_pack(2, ep, prefix + round_sum(rs)));
+      wave_hand_on(C, ws, cl.round, 0, true);
     }
   } else {
     to = !lds_wait_ge(C, &rs.pready, cl.round + 1);
@@ -2379,10 +2401,11 @@ __global__ GZ_WAVE_ATTR void k_encode_w(Job J, Ctl C) {
     const Claim cl = wave_claim(C, ws);
     RoundState& rs = ws.rs[cl.round % RING];
     if (cl.ticket >= NR) {  // past the end (or timed out)
+      if (cl.slot == 0 && __lane_id() == 0) wave_hand_on(C, ws, cl.round, cl.ticket, false);
       wave_release(rs);
       break;
     }
-    wave_round_unit<L, FUSED>(J, (uint64_t)cl.ticket * WaveEnc::WAVES + cl.slot, cl, rs,
+    wave_round_unit<L, FUSED>(J, (uint64_t)cl.ticket * WaveEnc::WAVES + cl.slot, cl, ws,
                               cl.ticket, 0, C, ep, R);
   }
   epilogue(C);
@@ -2401,13 +2424,14 @@ __global__ GZ_WAVE_ATTR void k_batch_encode_w(const Job* __restrict__ jobs, uint
     const Claim cl = wave_claim(C, ws);
     RoundState& rs = ws.rs[cl.round % RING];
     if (cl.ticket >= total) {  // past the end (or timed out)
+      if (cl.slot == 0 && __lane_id() == 0) wave_hand_on(C, ws, cl.round, cl.ticket, false);
       wave_release(rs);
       break;
     }
     const uint32_t j = cl.ticket % njobs;
     const Job J = jobs[j];
     const uint64_t NR = rounds_of(J.NS), r = cl.ticket / njobs;
-    wave_round_unit<L, FUSED>(J, r * WaveEnc::WAVES + cl.slot, cl, rs, j * NR + r, j * NR, C,
+    wave_round_unit<L, FUSED>(J, r * WaveEnc::WAVES + cl.slot, cl, ws, j * NR + r, j * NR, C,
                               ep, R);
   }
   epilogue(C);
