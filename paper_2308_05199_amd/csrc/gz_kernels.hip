@@ -1778,19 +1778,16 @@ __device__ bool wave_blocks_eval(const Job& J, uint64_t sb, uint64_t paydw, uint
   return __ballot(good) == ~0ull;
 }
 
-template <typename T, int L>
-__device__ __forceinline__ bool wave_blocks(const Job& J, const uint8_t* in, uint64_t sb,
-                                            uint64_t paydw, uint32_t nval, WaveBlocks& wb) {
-  uint32_t raw[3];
-  wave_blocks_load<L, false>(J, in, sb, raw);
-  return wave_blocks_eval<T, L>(J, sb, paydw, nval, raw, wb);
-}
 
 // Copies P payload dwords from src (global) into dst (LDS, 16-byte aligned),
 // realigned so that every load is a whole 16-byte chunk: only bytes inside
 // [16-byte floor of src, src + P) are read, and src lies past the stream's
 // fixed part.  Returns where src[0] landed (dst + 0..3).  MAXW bounds P.
-template <uint32_t MAXW>
+// UNROLL: straight-line code with uniform guards (a loop makes the compiler
+// wait for every outstanding memory operation at its head, the previous
+// stores included; the decoder gains, the fused step, short of registers,
+// does not).
+template <uint32_t MAXW, bool UNROLL>
 __device__ __forceinline__ const uint32_t* wave_stage_payload(const uint32_t* src, uint32_t P,
                                                               uint32_t* dst) {
   const uint32_t lane = __lane_id();
@@ -1799,13 +1796,27 @@ __device__ __forceinline__ const uint32_t* wave_stage_payload(const uint32_t* sr
   const uint32_t full = (delta + P) / 4, nch = (delta + P + 3) / 4;
   u4u* d4 = (u4u*)dst;
   constexpr uint32_t MAXCH = (MAXW + 3) / 4 + 1;
-  for (uint32_t k0 = 0; k0 < MAXCH && k0 < full; k0 += 8 * 64) {
-    u4u r[8];
+  if (UNROLL) {
 #pragma unroll
-    for (uint32_t u = 0; u < 8; ++u) r[u] = al[min(k0 + u * 64 + lane, full - 1)];
+    for (uint32_t k0 = 0; k0 < MAXCH; k0 += 8 * 64) {
+      if (k0 < full) {
+        u4u r[8];
 #pragma unroll
-    for (uint32_t u = 0; u < 8; ++u)
-      if (k0 + u * 64 + lane < full) d4[k0 + u * 64 + lane] = r[u];
+        for (uint32_t u = 0; u < 8; ++u) r[u] = al[min(k0 + u * 64 + lane, full - 1)];
+#pragma unroll
+        for (uint32_t u = 0; u < 8; ++u)
+          if (k0 + u * 64 + lane < full) d4[k0 + u * 64 + lane] = r[u];
+      }
+    }
+  } else {
+    for (uint32_t k0 = 0; k0 < MAXCH && k0 < full; k0 += 8 * 64) {
+      u4u r[8];
+#pragma unroll
+      for (uint32_t u = 0; u < 8; ++u) r[u] = al[min(k0 + u * 64 + lane, full - 1)];
+#pragma unroll
+      for (uint32_t u = 0; u < 8; ++u)
+        if (k0 + u * 64 + lane < full) d4[k0 + u * 64 + lane] = r[u];
+    }
   }
   if (full < nch && lane == 0) {
     const uint32_t* q = (const uint32_t*)(al + full);
@@ -1820,19 +1831,27 @@ __device__ __forceinline__ const uint32_t* wave_stage_payload(const uint32_t* sr
   return dst + delta;
 }
 
-// Decodes superblock sb into J.out; false (nothing written) if it is malformed.
+// Decodes superblock sb into J.out; false (nothing written) if it is
+// malformed.  raw: sb's table and header-byte words (wave_blocks_load), on
+// return those of the wave's next superblock nsb (if it exists), whose
+// loads go out with this superblock's payload copy.
 template <typename T, int L>
 __device__ bool wave_decode_super(const Job& J, const uint8_t* in, uint64_t sb, uint64_t paydw,
-                                  T t, uint32_t* R) {
+                                  T t, uint32_t* R, uint32_t (&raw)[3], uint64_t nsb) {
   constexpr uint32_t EW = sizeof(T) / 4, LPB = L / 32;
   constexpr uint32_t SEGW = 32 * EW, STR = seg_stride<T>();
   const uint32_t lane = __lane_id();
   const uint64_t e0 = sb * SUPER;
   const uint32_t nval = (uint32_t)min((uint64_t)SUPER, J.n - e0);
   WaveBlocks wb;
-  if (!wave_blocks<T, L>(J, in, sb, paydw, nval, wb)) return false;
-  const uint32_t* S = wave_stage_payload<SUPER * EW>(
-      (const uint32_t*)(in + J.pay_off) + wb.E, (uint32_t)(wb.En - wb.E), R);
+  const bool ok = wave_blocks_eval<T, L>(J, sb, paydw, nval, raw, wb);
+  const uint32_t* S = R;
+  if (ok)
+    S = wave_stage_payload<SUPER * EW, true>((const uint32_t*)(in + J.pay_off) + wb.E,
+                                             (uint32_t)(wb.En - wb.E), R);
+  // the next superblock's words are in flight during this one's unpacking
+  if (nsb < J.NS) wave_blocks_load<L, false>(J, in, nsb, raw);
+  if (!ok) return false;
   wave_lds_sync();
   const uint32_t* boff = wb.boff;
   const uint32_t* kind = wb.kind;
@@ -1905,8 +1924,11 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1, 2))) void k_decompres
   bool bad = !wave_header<T>(J, in, paydw, t);
   if (!bad) {
     const uint64_t W = (uint64_t)gridDim.x * (blockDim.x >> 6);
-    for (uint64_t sb = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wid; sb < J.NS; sb += W)
-      if (!wave_decode_super<T, L>(J, in, sb, paydw, t, R)) bad = true;
+    const uint64_t sb0 = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wid;
+    uint32_t raw[3] = {0u, 0u, 0u};
+    if (sb0 < J.NS) wave_blocks_load<L, false>(J, in, sb0, raw);
+    for (uint64_t sb = sb0; sb < J.NS; sb += W)
+      if (!wave_decode_super<T, L>(J, in, sb, paydw, t, R, raw, sb + W)) bad = true;
   }
   if (bad && __lane_id() == 0) atomicOr(&C.ctrl->err, ERRF_CORRUPT);
 }
@@ -2069,7 +2091,7 @@ __device__ __forceinline__ void wave_encode_unit(const Job& J, uint64_t u, uint3
       const uint32_t hoff = (h && !whole) ? wb.half0 : 0u;
       if (good && (h == 0 || !whole)) {
         const uint32_t P = whole ? Ptot : (h ? Ptot - wb.half0 : wb.half0);
-        S = wave_stage_payload<SUPER>(fs.pay + wb.E + hoff, P, X);
+        S = wave_stage_payload<SUPER, false>(fs.pay + wb.E + hoff, P, X);
       }
       // the addend's loads are in flight during the decode
       u4u lr[8];
