@@ -318,8 +318,9 @@ gz_status gz_mlp_adam(gz_ctx* ctx, float* d_w, const float* d_grad, float* d_m,
  * available (GZ_EINVAL).  The workspace is a device-resident array of
  * 263,424 bytes that the library holds on each device until the process
  * ends; it serves streams of at most 32768 strips (2^30 fp32 elements at the
- * default 1024 threads, 2^28 fp64 elements at 256), larger inputs return
- * GZ_ENOSPC with nothing enqueued.  The call allocates nothing: its first
+ * default 1024 threads, 2^28 fp64 elements at 256) or, with threads 64,
+ * 32768 rounds of 8 superblocks (also 2^30 fp32 elements); larger inputs
+ * return GZ_ENOSPC with nothing enqueued.  The call allocates nothing: its first
  * call on a device only looks up the array's address.  It enqueues the
  * compression and a one-wave kernel that writes the device status of the
  * call (GZ_OK, or GZ_ETIMEOUT when a look-back wait expired and the stream

@@ -89,6 +89,18 @@ def test_noalloc_thread_counts_and_tiles(gz, ctx, tpb):
         both(gz, ctx, t, 1e-4, block_len=64, threads=tpb, mode=1, select=select, nx=nx)
 
 
+@pytest.mark.parametrize("L", [32, 128])
+def test_noalloc_per_wave_encoder_twice(gz, ctx, L):
+    """threads 64: the per-wave encoder on the device-resident workspace (one
+    look-back word per round of 8 superblocks), two calls in a row, the
+    second smaller; bytes equal the context path's."""
+    import torch
+    for n, seed in ((70 * 4096 + 77, 8), (12_345, 9)):
+        say("noalloc per-wave", "L", L, "n", n)
+        x = torch.from_numpy(field(n, seed, np.float32)).cuda()
+        both(gz, ctx, x, 1e-4, block_len=L, threads=64)
+
+
 def test_noalloc_allocates_nothing_and_rejects(gz, ctx):
     import torch
     say("noalloc memory and limits")
