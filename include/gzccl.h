@@ -77,9 +77,11 @@ typedef struct gz_graph gz_graph;
  * GZ_EUNSUPPORTED) and grid (persistent workgroups, 0 = default) never change
  * the bytes.  threads 64 selects the per-wave kernels, in which each wave
  * codes whole 4096-element superblocks on its own (grid ignored): 1D
- * decompression of either type, fp32 1D compression and the fused step;
- * GZ_EUNSUPPORTED elsewhere.  With no shape given or tuned, decompression
- * and the fused step take them, compression takes strips.  mode 0 = 1D blocks, 1 = 8x8 tiles (block_len 64,
+ * decompression of either type (also batched and scatter), fp32 1D
+ * compression, the fused step and decode-and-accumulate; GZ_EUNSUPPORTED
+ * elsewhere.  With no shape given or tuned, decompression (single and
+ * batched) and the fused step take them; compression, decode-and-accumulate
+ * and scatter decompression take strips.  mode 0 = 1D blocks, 1 = 8x8 tiles (block_len 64,
  * nx = row length, multiple of 8, n a multiple of 8*nx); select (mode 1):
  * 0 = int8 MLP selector, 1 = exhaustive trial, 2 = always L1D. */
 typedef struct {

@@ -109,6 +109,8 @@ struct gz_plan {
   uint32_t tpb = 0, grid = 0;
   bool wide = false;
   bool wave = false;  // per-wave encoding kernels (total = njobs x rounds)
+  bool wave_dec = false;  // per-wave decoding kernels (total = superblocks)
+  bool has_map = false;   // wave_dec: d_map lists (job, superblock) pairs
   uint32_t log2L = 5;
 };
 
@@ -250,16 +252,20 @@ bool params_ok(const gz_params* p, uint32_t& L) {
 
 bool tile_mode(const gz_params* p) { return p && p->mode == 1; }
 
-// Per-wave kernels exist for 1D decoding of either type (op 1) and fp32 1D
-// encoding and the fused step (ops 0, 2), and need their LDS.
+// Per-wave kernels exist for 1D decoding of either type (op 1), fp32 1D
+// encoding, the fused step and decode-and-accumulate (ops 0, 2, 3), and
+// need their LDS.
 bool wave_fits(const gz_ctx* c, uint32_t op, uint32_t dt) {
   if (op == 1) return gzk::wave_decode_lds(dt) <= c->lds_max;
+  if (op == 3) return dt == GZ_F32 && gzk::wave_decode_lds(GZ_F32) <= c->lds_max;
   return (op == 0 || op == 2) && dt == GZ_F32 && gzk::wave_encode_lds() <= c->lds_max;
 }
 
-// Measured defaults: the per-wave kernels for decoding and the fused step,
-// strips for compression (faster there: four waves per SIMD hide the input
-// loads, where the per-wave encoder has two).
+// Measured defaults: the per-wave kernels for decoding (single streams and
+// batches) and the fused step; strips for compression and decode-and-
+// accumulate (1 GiB: 417 vs 455 us and 436 vs 478 us; there four waves per
+// SIMD hide the input and accumulator loads, where the per-wave kernels
+// have two) and for scatter decoding (an offset read per superblock).
 bool wave_default(uint32_t op) { return op == 1 || op == 2; }
 
 // Whether a single 1D call takes the per-wave kernel: asked for (threads
@@ -405,11 +411,44 @@ bool batch_wave_ok(const gz_ctx* c, gz_op op, const std::vector<Job>& jobs) {
 
 // Whether a batch takes the per-wave kernels when it can: asked for
 // (threads 64), tuned, or by default.
-bool batch_wave_wanted(const gz_ctx* c, gz_op op, const gz_params* p) {
+bool batch_wave_wanted(const gz_ctx* c, gz_op op, const gz_params* p, bool wide = false) {
   if (p && p->threads) return p->threads == WAVE_TPB;
   if (p && p->grid) return false;
-  const Tuned& t = c->batch_tuned[op][0];
+  const Tuned& t = c->batch_tuned[op][wide ? 1 : 0];
   return t.tpb ? t.tpb == WAVE_TPB : wave_default(op);
+}
+
+// The superblocks of a per-wave decoding batch as (job, superblock) pairs,
+// job by job; none when every job has the same superblock count (the kernel
+// then derives them).  Returns the number of superblocks.
+uint64_t wave_decode_map(const std::vector<Job>& jobs, std::vector<uint32_t>& map) {
+  map.clear();
+  uint64_t total = 0;
+  bool uniform = true;
+  for (const Job& J : jobs) {
+    total += J.NS;
+    uniform = uniform && J.NS == jobs[0].NS;
+  }
+  if (uniform || total > (1ull << 31)) return total;
+  map.reserve(2 * total);
+  for (uint32_t j = 0; j < (uint32_t)jobs.size(); ++j)
+    for (uint64_t sb = 0; sb < jobs[j].NS; ++sb) {
+      map.push_back(j);
+      map.push_back((uint32_t)sb);
+    }
+  return total;
+}
+
+// A batch the per-wave decoders take: decoding, or fp32 decode-and-
+// accumulate, every job with at least one superblock (an empty stream's
+// header is checked by a strip), within the context's map capacity.
+bool batch_decode_wave_ok(const gz_ctx* c, gz_op op, const std::vector<Job>& jobs, bool wide,
+                          uint64_t total) {
+  if (op != GZ_OP_DECOMPRESS && op != GZ_OP_ACCUMULATE) return false;
+  if (!wave_fits(c, op, wide ? GZ_F64 : GZ_F32)) return false;
+  for (const Job& J : jobs)
+    if (J.NS == 0) return false;
+  return total > 0 && total <= c->max_strips && total < (1ull << 32);
 }
 
 uint32_t batch_grid(const gz_ctx* c, gz_op op, bool wide, uint32_t tpb, uint64_t total,
@@ -732,13 +771,17 @@ gz_status gz_decompress_add(gz_ctx* c, const void* d_in, uint64_t in_bytes, uint
   Job J;
   memset(&J, 0, sizeof J);
   J.dtype = GZ_F32;
+  J.in = job_ptr(d_in);
+  J.in_bytes = in_bytes;
+  J.out = job_ptr(d_acc);
+  if (wave_wanted(c, 3, GZ_F32, L, p) && wave_fits(c, 3, GZ_F32)) {
+    set_geom(J, n, L, gzk::MAX_TPB);
+    return hip_status(gzk::launch_accum_wave(J, c->ctl(), (uint32_t)c->cus, (hipStream_t)stream));
+  }
   const uint32_t tpb = pick_tpb(c, 3, GZ_F32, L, p);
   if (!tpb_fits(c, false, false, tpb)) return GZ_EUNSUPPORTED;
   set_geom(J, n, L, tpb);
   if (J.nstrips > c->max_strips) return GZ_ENOSPC;
-  J.in = job_ptr(d_in);
-  J.in_bytes = in_bytes;
-  J.out = job_ptr(d_acc);
   const uint32_t grid = pick_grid(c, 3, GZ_F32, L, tpb, J.nstrips, p);
   return hip_status(gzk::launch_single(3, J, c->ctl(), tpb, grid, (hipStream_t)stream));
 }
@@ -805,8 +848,15 @@ gz_status gz_scatter_decompress(gz_ctx* c, const void* d_packed, uint64_t packed
       (dtype != GZ_F32 && dtype != GZ_F64) || !params_ok(p, L) || tile_mode(p) || nchunks == 0)
     return GZ_EINVAL;
   if (nchunks > c->max_jobs) return GZ_ENOSPC;
-  const uint32_t tpb = pick_tpb(c, 1, dtype, L, p);
-  if (!tpb_fits(c, dtype == GZ_F64, false, tpb)) return GZ_EUNSUPPORTED;
+  const bool want_wave = p && p->threads == WAVE_TPB && wave_fits(c, 1, dtype);
+  gz_params q;  // the strips' shape when waves were asked for (geometry, fallback)
+  const gz_params* ps = p;
+  if (p && p->threads == WAVE_TPB) {
+    q = *p;
+    q.threads = q.grid = 0;
+    ps = &q;
+  }
+  const uint32_t tpb = pick_tpb(c, 1, dtype, L, ps);
   std::vector<Job> jobs(nchunks);
   uint64_t strip = 0, span = 0;
   for (uint32_t j = 0; j < nchunks; ++j) {
@@ -828,12 +878,25 @@ gz_status gz_scatter_decompress(gz_ctx* c, const void* d_packed, uint64_t packed
   }
   if (strip > c->max_strips) return GZ_ENOSPC;
   if (overlaps(d_packed, packed_bytes, d_root, span * esize(dtype))) return GZ_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  if (want_wave) {
+    std::vector<uint32_t> smap;
+    const uint64_t total = wave_decode_map(jobs, smap);
+    if (batch_decode_wave_ok(c, GZ_OP_DECOMPRESS, jobs, dtype == GZ_F64, total)) {
+      gz_status r = stage_upload(c, jobs, smap, st);
+      if (r != GZ_OK) return r;
+      return hip_status(gzk::launch_decode_wave_batch(
+          1, c->d_jobs, smap.empty() ? nullptr : c->d_map, nchunks, (uint32_t)total,
+          dtype == GZ_F64, (uint32_t)c->cus, c->ctl(), st));
+    }
+    if (p && p->threads == WAVE_TPB) return GZ_EUNSUPPORTED;
+  }
+  if (!tpb_fits(c, dtype == GZ_F64, false, tpb)) return GZ_EUNSUPPORTED;
   std::vector<uint32_t> map;
   fill_map(jobs, true, map);
-  hipStream_t st = (hipStream_t)stream;
   gz_status r = stage_upload(c, jobs, map, st);
   if (r != GZ_OK) return r;
-  const uint32_t grid = pick_grid(c, 1, dtype, L, tpb, strip, p);
+  const uint32_t grid = pick_grid(c, 1, dtype, L, tpb, strip, ps);
   return hip_status(gzk::launch_batch(1, c->d_jobs, c->d_map, uniform_jobs(jobs), (uint32_t)strip,
                                       c->ctl(), tpb,
                                       grid, dtype == GZ_F64, st));
@@ -851,9 +914,21 @@ gz_status gz_batch(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t nreq,
   std::vector<uint32_t> map;
   gz_status r = build_requests(c, op, h_reqs, nreq, tpb, jobs, map);
   if (r != GZ_OK) return r;
+  hipStream_t st = (hipStream_t)stream;
+  if ((op == GZ_OP_DECOMPRESS || op == GZ_OP_ACCUMULATE) && batch_wave_wanted(c, op, p, wide)) {
+    std::vector<uint32_t> smap;
+    const uint64_t total = wave_decode_map(jobs, smap);
+    if (batch_decode_wave_ok(c, op, jobs, wide, total)) {
+      r = stage_upload(c, jobs, smap, st);
+      if (r != GZ_OK) return r;
+      return hip_status(gzk::launch_decode_wave_batch(
+          (uint32_t)op, c->d_jobs, smap.empty() ? nullptr : c->d_map, (uint32_t)jobs.size(),
+          (uint32_t)total, wide, (uint32_t)c->cus, c->ctl(), st));
+    }
+    if (p && p->threads == WAVE_TPB) return GZ_EUNSUPPORTED;
+  }
   const bool wave = !wide && batch_wave_wanted(c, op, p) && batch_wave_ok(c, op, jobs);
   if (p && p->threads == WAVE_TPB && !wave) return GZ_EUNSUPPORTED;
-  hipStream_t st = (hipStream_t)stream;
   r = stage_upload(c, jobs, map, st);
   if (r != GZ_OK) return r;
   if (wave)
@@ -880,14 +955,23 @@ gz_status gz_plan_create(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t
   std::vector<uint32_t> map;
   gz_status r = build_requests(c, op, h_reqs, nreq, tpb, jobs, map);
   if (r != GZ_OK) return r;
-  const bool wave = !wide && batch_wave_wanted(c, op, p) && batch_wave_ok(c, op, jobs);
-  if (p && p->threads == WAVE_TPB && !wave) return GZ_EUNSUPPORTED;
+  bool wave_dec = false;
+  uint64_t dec_total = 0;
+  if ((op == GZ_OP_DECOMPRESS || op == GZ_OP_ACCUMULATE) && batch_wave_wanted(c, op, p, wide)) {
+    std::vector<uint32_t> smap;
+    dec_total = wave_decode_map(jobs, smap);
+    wave_dec = batch_decode_wave_ok(c, op, jobs, wide, dec_total);
+    if (wave_dec) map.swap(smap);
+    else if (p && p->threads == WAVE_TPB) return GZ_EUNSUPPORTED;
+  }
+  const bool wave = !wave_dec && !wide && batch_wave_wanted(c, op, p) && batch_wave_ok(c, op, jobs);
+  if (p && p->threads == WAVE_TPB && !wave && !wave_dec) return GZ_EUNSUPPORTED;
   // a range released by gz_plan_destroy may still be read by a launch in
   // flight: the device finishes its work before the arena is written
   if (hipDeviceSynchronize() != hipSuccess) return GZ_EHIP;
   uint64_t jo = 0, mo = 0;
   if (!c->plan_jobs_arena.take(jobs.size(), jo)) return GZ_ENOSPC;
-  if (!c->plan_map_arena.take(map.size(), mo)) {
+  if (!c->plan_map_arena.take(std::max<size_t>(map.size(), 1), mo)) {
     c->plan_jobs_arena.give(jo);
     return GZ_ENOSPC;
   }
@@ -914,10 +998,17 @@ gz_status gz_plan_create(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t
     pl->total = (uint32_t)(jobs.size() * gzk::wave_rounds(jobs[0].NS));
     pl->log2L = jobs[0].log2L;
   }
+  if (wave_dec) {
+    pl->wave_dec = true;
+    pl->has_map = !map.empty();
+    pl->njobs = (uint32_t)jobs.size();
+    pl->total = (uint32_t)dec_total;
+  }
   c->live_plans.push_back(pl);
   if (hipMemcpy(pl->d_jobs, jobs.data(), jobs.size() * sizeof(Job), hipMemcpyHostToDevice) !=
           hipSuccess ||
-      hipMemcpy(pl->d_map, map.data(), map.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+      (!map.empty() &&
+       hipMemcpy(pl->d_map, map.data(), map.size() * 4, hipMemcpyHostToDevice) != hipSuccess)) {
     gz_plan_destroy(pl);
     return GZ_EHIP;
   }
@@ -931,6 +1022,10 @@ gz_status gz_plan_launch(gz_plan* pl, gz_stream_t stream) {
     return hip_status(gzk::launch_encode_wave(pl->op, pl->d_jobs, Job(), pl->njobs, pl->total,
                                               pl->log2L, pl->ctx->ctl(),
                                               (uint32_t)pl->ctx->cus, (hipStream_t)stream));
+  if (pl->wave_dec)
+    return hip_status(gzk::launch_decode_wave_batch(
+        pl->op, pl->d_jobs, pl->has_map ? pl->d_map : nullptr, pl->njobs, pl->total, pl->wide,
+        (uint32_t)pl->ctx->cus, pl->ctx->ctl(), (hipStream_t)stream));
   return hip_status(gzk::launch_batch(pl->op, pl->d_jobs, pl->d_map, pl->njobs, pl->total,
                                       pl->ctx->ctl(),
                                       pl->tpb, pl->grid, pl->wide, (hipStream_t)stream));
@@ -1154,12 +1249,17 @@ gz_status gz_tune_batch(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t 
   gz_status r = GZ_OK;
   // the per-wave kernels are a candidate where the batch qualifies
   bool wave_ok = false;
-  if (!wide) {
+  {
     std::vector<Job> jobs;
     std::vector<uint32_t> map;
-    r = build_requests(c, op, h_reqs, nreq, gzk::MAX_TPB, jobs, map);
+    r = build_requests(c, op, h_reqs, nreq, gzk::MAX_TPB_WIDE, jobs, map);
     if (r != GZ_OK) return r;
-    wave_ok = batch_wave_ok(c, op, jobs);
+    if (op == GZ_OP_DECOMPRESS) {
+      std::vector<uint32_t> smap;
+      wave_ok = batch_decode_wave_ok(c, op, jobs, wide, wave_decode_map(jobs, smap));
+    } else if (!wide) {
+      wave_ok = batch_wave_ok(c, op, jobs);
+    }
   }
   if (!(cache_lookup(cache_path, keyb, tpb, grid) &&
         (tpb_fits(c, wide, false, tpb) || (tpb == WAVE_TPB && wave_ok)))) {

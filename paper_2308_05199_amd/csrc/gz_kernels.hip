@@ -1831,18 +1831,28 @@ __device__ __forceinline__ const uint32_t* wave_stage_payload(const uint32_t* sr
   return dst + delta;
 }
 
-// Decodes superblock sb into J.out; false (nothing written) if it is
+// Decodes superblock sb into J.out (OP 1), or adds it to the fp32 values
+// there (OP 3, decode-and-accumulate); false (nothing written) if it is
 // malformed.  raw: sb's table and header-byte words (wave_blocks_load), on
 // return those of the wave's next superblock nsb (if it exists), whose
 // loads go out with this superblock's payload copy.
-template <typename T, int L>
+template <typename T, int L, uint32_t OP = 1>
 __device__ bool wave_decode_super(const Job& J, const uint8_t* in, uint64_t sb, uint64_t paydw,
                                   T t, uint32_t* R, uint32_t (&raw)[3], uint64_t nsb) {
+  static_assert(OP == 1 || (OP == 3 && sizeof(T) == 4), "accumulation is fp32");
   constexpr uint32_t EW = sizeof(T) / 4, LPB = L / 32;
   constexpr uint32_t SEGW = 32 * EW, STR = seg_stride<T>();
+  constexpr uint32_t CPL = SUPER * EW / 4 / 64;  // 16-byte chunks per lane of a superblock
   const uint32_t lane = __lane_id();
   const uint64_t e0 = sb * SUPER;
   const uint32_t nval = (uint32_t)min((uint64_t)SUPER, J.n - e0);
+  uint32_t* d32 = (uint32_t*)((T*)J.out + e0);
+  // OP 3: the accumulator of a whole superblock is in flight during the decode
+  u4u old[OP == 3 ? CPL : 1];
+  if (OP == 3 && nval == SUPER) {
+#pragma unroll
+    for (uint32_t u = 0; u < CPL; ++u) old[u] = ((const u4u*)d32)[u * 64 + lane];
+  }
   WaveBlocks wb;
   const bool ok = wave_blocks_eval<T, L>(J, sb, paydw, nval, raw, wb);
   const uint32_t* S = R;
@@ -1887,25 +1897,39 @@ __device__ bool wave_decode_super(const Job& J, const uint8_t* in, uint64_t sb, 
     }
   }
   wave_lds_sync();
-  uint32_t* d32 = (uint32_t*)((T*)J.out + e0);
   const uint32_t vdw = nval * EW;
+  // decoded + old, in fp32 (OP 3)
+  auto addf = [](uint32_t a, uint32_t b) { return __float_as_uint(__uint_as_float(a) + __uint_as_float(b)); };
   if (nval == SUPER) {
 #pragma unroll
-    for (uint32_t u = 0; u < SUPER * EW / 4 / 64; ++u) {  // 16 (fp32) or 32 (fp64) chunks per lane
+    for (uint32_t u = 0; u < CPL; ++u) {  // 16 (fp32) or 32 (fp64) chunks per lane
       const uint32_t k = u * 64 + lane, dw = 4 * k;
-      const u4u r = *(const u4u*)(R + (dw / SEGW) * STR + dw % SEGW);
+      u4u r = *(const u4u*)(R + (dw / SEGW) * STR + dw % SEGW);
+      if (OP == 3) {
+        r.x = addf(r.x, old[u].x);
+        r.y = addf(r.y, old[u].y);
+        r.z = addf(r.z, old[u].z);
+        r.w = addf(r.w, old[u].w);
+      }
       ((u4u*)d32)[k] = r;
     }
   } else {
     for (uint32_t k = lane; 4 * k < vdw; k += 64) {
       const uint32_t dw = 4 * k;
-      const u4u r = *(const u4u*)(R + (dw / SEGW) * STR + dw % SEGW);
+      u4u r = *(const u4u*)(R + (dw / SEGW) * STR + dw % SEGW);
       if (dw + 4 <= vdw) {
+        if (OP == 3) {
+          const u4u a = ((const u4u*)d32)[k];
+          r.x = addf(r.x, a.x);
+          r.y = addf(r.y, a.y);
+          r.z = addf(r.z, a.z);
+          r.w = addf(r.w, a.w);
+        }
         ((u4u*)d32)[k] = r;
       } else {
-        if (dw + 0 < vdw) d32[dw + 0] = r.x;
-        if (dw + 1 < vdw) d32[dw + 1] = r.y;
-        if (dw + 2 < vdw) d32[dw + 2] = r.z;
+        if (dw + 0 < vdw) d32[dw + 0] = OP == 3 ? addf(r.x, d32[dw + 0]) : r.x;
+        if (dw + 1 < vdw) d32[dw + 1] = OP == 3 ? addf(r.y, d32[dw + 1]) : r.y;
+        if (dw + 2 < vdw) d32[dw + 2] = OP == 3 ? addf(r.z, d32[dw + 2]) : r.z;
       }
     }
   }
@@ -1929,6 +1953,79 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1, 2))) void k_decompres
     if (sb0 < J.NS) wave_blocks_load<L, false>(J, in, sb0, raw);
     for (uint64_t sb = sb0; sb < J.NS; sb += W)
       if (!wave_decode_super<T, L>(J, in, sb, paydw, t, R, raw, sb + W)) bad = true;
+  }
+  if (bad && __lane_id() == 0) atomicOr(&C.ctrl->err, ERRF_CORRUPT);
+}
+
+// Single-stream decode-and-accumulate by waves (fp32): as k_decompress_w,
+// each superblock added to the accumulator J.out.
+template <int L>
+__global__ __launch_bounds__(WaveDec<float>::WAVES * 64)
+__attribute__((amdgpu_waves_per_eu(2, 2))) void k_accum_w(Job J, Ctl C) {
+  const uint32_t wid = threadIdx.x >> 6;
+  uint32_t* R = g_stage + wid * WaveDec<float>::REGION;
+  const uint8_t* in = (const uint8_t*)J.in;
+  uint64_t paydw = 0;
+  float t = 0;
+  bool bad = !wave_header<float>(J, in, paydw, t);
+  if (!bad) {
+    const uint64_t W = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    const uint64_t sb0 = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wid;
+    uint32_t raw[3] = {0u, 0u, 0u};
+    if (sb0 < J.NS) wave_blocks_load<L, false>(J, in, sb0, raw);
+    for (uint64_t sb = sb0; sb < J.NS; sb += W)
+      if (!wave_decode_super<float, L, 3>(J, in, sb, paydw, t, R, raw, sb + W)) bad = true;
+  }
+  if (bad && __lane_id() == 0) atomicOr(&C.ctrl->err, ERRF_CORRUPT);
+}
+
+// One superblock of a batch job: the job's stream (at its scatter offset,
+// if any) is checked and the superblock decoded (OP 1) or accumulated (OP 3).
+template <typename T, int L, uint32_t OP>
+__device__ __forceinline__ bool wave_batch_super(const Job& J, uint64_t sb, uint32_t* R) {
+  const uint64_t off = J.in_off ? J.in_off[J.job] : 0ull;
+  Job Jl = J;
+  Jl.in_bytes = off <= J.in_bytes ? J.in_bytes - off : 0ull;
+  const uint8_t* in = (const uint8_t*)J.in + off;
+  uint32_t raw[3];
+  wave_blocks_load<L, true>(Jl, in, sb, raw);  // in flight with the header's words
+  uint64_t paydw = 0;
+  T t = 0;
+  if (!wave_header<T>(Jl, in, paydw, t)) return false;
+  return wave_decode_super<T, L, OP>(Jl, in, sb, paydw, t, R, raw, ~0ull);
+}
+
+// Batched decoding (OP 1) or decode-and-accumulate (OP 3) by waves: batch
+// superblock i is superblock map[2i + 1] of job map[2i], or, without a map
+// (jobs of equal superblock counts), superblock i / njobs of job i % njobs;
+// waves take them statically.  WIDE: the batch holds fp64 jobs (fp64-sized
+// regions, four waves per workgroup).
+template <bool WIDE, uint32_t OP>
+__global__ __launch_bounds__((WIDE ? WaveDec<double>::WAVES : WaveDec<float>::WAVES) * 64)
+__attribute__((amdgpu_waves_per_eu(WIDE ? 1 : 2, 2))) void k_batch_decode_w(
+    const Job* __restrict__ jobs, const uint32_t* __restrict__ map, uint32_t njobs,
+    uint32_t total, Ctl C) {
+  constexpr uint32_t WAVES = WIDE ? WaveDec<double>::WAVES : WaveDec<float>::WAVES;
+  constexpr uint32_t REGION = WIDE ? WaveDec<double>::REGION : WaveDec<float>::REGION;
+  const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  uint32_t* R = g_stage + wid * REGION;
+  bool bad = false;
+  const uint32_t W = gridDim.x * WAVES;
+  for (uint32_t i = blockIdx.x * WAVES + wid; i < total; i += W) {
+    const uint32_t j = map ? map[2 * (uint64_t)i] : i % njobs;
+    const uint64_t sb = map ? map[2 * (uint64_t)i + 1] : i / njobs;
+    const Job J = jobs[j];
+    bool ok = false;
+    switch ((J.dtype << 3) | J.log2L) {
+      case 5: ok = wave_batch_super<float, 32, OP>(J, sb, R); break;
+      case 6: ok = wave_batch_super<float, 64, OP>(J, sb, R); break;
+      case 7: ok = wave_batch_super<float, 128, OP>(J, sb, R); break;
+      case 13: if constexpr (WIDE && OP == 1) ok = wave_batch_super<double, 32, 1>(J, sb, R); break;
+      case 14: if constexpr (WIDE && OP == 1) ok = wave_batch_super<double, 64, 1>(J, sb, R); break;
+      case 15: if constexpr (WIDE && OP == 1) ok = wave_batch_super<double, 128, 1>(J, sb, R); break;
+      default: break;
+    }
+    if (!ok) bad = true;
   }
   if (bad && __lane_id() == 0) atomicOr(&C.ctrl->err, ERRF_CORRUPT);
 }
@@ -2855,6 +2952,46 @@ hipError_t launch_encode_wave(uint32_t op, const Job* d_jobs, const Job& J, uint
     case 7: return fused ? launch_ew<128, true>(d_jobs, J, njobs, total, C, cus, st)
                          : launch_ew<128, false>(d_jobs, J, njobs, total, C, cus, st);
   }
+  return hipErrorInvalidValue;
+}
+
+template <int L>
+static hipError_t launch_aw(const Job& J, const Ctl& C, uint32_t grid, hipStream_t st) {
+  const size_t lds = (size_t)WaveDec<float>::WAVES * WaveDec<float>::REGION * 4;
+  hipLaunchKernelGGL((k_accum_w<L>), dim3(grid), dim3(WaveDec<float>::WAVES * 64), lds, st, J, C);
+  return hipGetLastError();
+}
+
+hipError_t launch_accum_wave(const Job& J, const Ctl& C, uint32_t cus, hipStream_t st) {
+  const uint64_t need = (J.NS + WaveDec<float>::WAVES - 1) / WaveDec<float>::WAVES;
+  const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(cus, need));
+  switch (J.log2L) {
+    case 5: return launch_aw<32>(J, C, grid, st);
+    case 6: return launch_aw<64>(J, C, grid, st);
+    case 7: return launch_aw<128>(J, C, grid, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <bool WIDE, uint32_t OP>
+static hipError_t launch_bdw(const Job* d_jobs, const uint32_t* d_map, uint32_t njobs,
+                             uint32_t total, uint32_t cus, const Ctl& C, hipStream_t st) {
+  constexpr uint32_t WAVES = WIDE ? WaveDec<double>::WAVES : WaveDec<float>::WAVES;
+  const size_t lds = (size_t)WAVES * (WIDE ? WaveDec<double>::REGION : WaveDec<float>::REGION) * 4;
+  const uint64_t need = ((uint64_t)total + WAVES - 1) / WAVES;
+  const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(cus, need));
+  hipLaunchKernelGGL((k_batch_decode_w<WIDE, OP>), dim3(grid), dim3(WAVES * 64), lds, st, d_jobs,
+                     d_map, njobs, total, C);
+  return hipGetLastError();
+}
+
+hipError_t launch_decode_wave_batch(uint32_t op, const Job* d_jobs, const uint32_t* d_map,
+                                    uint32_t njobs, uint32_t total, bool wide, uint32_t cus,
+                                    const Ctl& C, hipStream_t st) {
+  if (op == 1)
+    return wide ? launch_bdw<true, 1>(d_jobs, d_map, njobs, total, cus, C, st)
+                : launch_bdw<false, 1>(d_jobs, d_map, njobs, total, cus, C, st);
+  if (op == 3 && !wide) return launch_bdw<false, 3>(d_jobs, d_map, njobs, total, cus, C, st);
   return hipErrorInvalidValue;
 }
 

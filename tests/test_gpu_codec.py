@@ -209,7 +209,8 @@ def test_fused_minus_zero_identity(ctx):
 
 
 @pytest.mark.parametrize("dt", [np.float32, np.float64])
-def test_scatter_matches_oracle(ctx, oracle, dt):
+@pytest.mark.parametrize("tpb", [0, 64])   # strip (default) and per-wave decoding
+def test_scatter_matches_oracle(ctx, oracle, dt, tpb):
     import torch
     say("scatter", dt.__name__)
     n = 300_000
@@ -225,7 +226,7 @@ def test_scatter_matches_oracle(ctx, oracle, dt):
     # batched decompression of all chunks back into one buffer
     y = ctx.scatter_decompress(out, torch.from_numpy(co).cuda(), counts, displs,
                                dtype=torch.float32 if dt == np.float32 else torch.float64,
-                               block_len=64, packed_bytes=total)
+                               block_len=64, packed_bytes=total, threads=tpb)
     torch.cuda.synchronize()
     ref = np.concatenate([oracle.decompress(want[wco[j]:wco[j] + wcb[j]])
                           for j in range(len(counts))])
@@ -276,10 +277,14 @@ def test_batch_compress_decompress(ctx, oracle, gz):
         items.append(dict(**{"in": s}, out=y, n=r["n"], in_bytes=s.numel(), dtype=dt,
                           block_len=r["block_len"]))
     arr = ctx.requests(items)
-    ctx.batch(gz.GZ_OP_DECOMPRESS, arr)
-    torch.cuda.synchronize()
-    for s, y in zip(streams, ys):
-        assert y.cpu().numpy().tobytes() == oracle.decompress(s.cpu().numpy()).tobytes()
+    wants = [oracle.decompress(s.cpu().numpy()) for s in streams]
+    for tpb in (0, 64, 512):  # default and 64: per-wave with a superblock map; 512: strips
+        for y in ys:
+            y.fill_(-1.0)
+        ctx.batch(gz.GZ_OP_DECOMPRESS, arr, threads=tpb)
+        torch.cuda.synchronize()
+        for w, y in zip(wants, ys):
+            assert y.cpu().numpy().tobytes() == w.tobytes(), tpb
     assert_ok(ctx)
 
 
@@ -388,14 +393,22 @@ def test_argument_errors(ctx, gz):
     with pytest.raises(gz.GzError) as e:
         ctx.compress(torch.zeros(100, dtype=torch.float64, device="cuda"), 1e-3, threads=1024)
     assert e.value.status == gz.GZ_EUNSUPPORTED
-    # the per-wave kernels (threads 64): no fp64 encoder, no accumulate
+    # the per-wave kernels (threads 64): no fp64 encoder, no scatter encoder,
+    # no tiles
     with pytest.raises(gz.GzError) as e:
         ctx.compress(torch.zeros(100, dtype=torch.float64, device="cuda"), 1e-3, threads=64)
     assert e.value.status == gz.GZ_EUNSUPPORTED
-    s64, nb64 = ctx.compress(x, 1e-3)
     with pytest.raises(gz.GzError) as e:
-        ctx.decompress_add(s64, torch.zeros(100, device="cuda"), threads=64)
+        ctx.scatter_compress(torch.zeros(1000, device="cuda"), [500, 500], [0, 500], 1e-3,
+                             threads=64)
     assert e.value.status == gz.GZ_EUNSUPPORTED
+    p64 = gz.gz_params(64, 64, 0, 1, 2, 64)
+    x64 = torch.zeros(64 * 64, device="cuda")
+    o64 = torch.empty(1 << 16, dtype=torch.uint8, device="cuda")
+    b64 = torch.zeros(1, dtype=torch.int64, device="cuda")
+    st64 = gz.gz_compress(ctx.h, gz._ptr(x64), x64.numel(), gz.GZ_F32, 1e-3, ctypes.byref(p64),
+                          gz._ptr(o64), o64.numel(), gz._ptr(b64), gz._stream(None))
+    assert st64 == gz.GZ_EUNSUPPORTED
     xt = torch.zeros(64 * 64, device="cuda")
     cap = gz.bound(xt.numel(), gz.GZ_F32, 64)
     out = torch.empty(cap, dtype=torch.uint8, device="cuda")
@@ -539,6 +552,22 @@ def test_wave_batches_match_oracle(ctx, oracle, gz, L):
         torch.cuda.synchronize()
         for w, f, b in zip(want_f, fo, fb):
             assert f[:int(b.item())].cpu().numpy().tobytes() == w.tobytes(), tpb
+    # the streams back: a uniform batch (no superblock map) on the per-wave
+    # decoders, then decode-and-accumulate onto the inputs
+    ys = [torch.full((n,), -1.0, device="cuda") for n in ns]
+    ditems = [dict(**{"in": o}, out=y, n=n, in_bytes=int(b.item()), dtype=gz.GZ_F32, block_len=L)
+              for o, y, n, b in zip(outs, ys, ns, nbs)]
+    ctx.batch(gz.GZ_OP_DECOMPRESS, ctx.requests(ditems), threads=64)
+    torch.cuda.synchronize()
+    for w, y in zip(want, ys):
+        assert y.cpu().numpy().tobytes() == oracle.decompress(w).tobytes()
+    accs = [dev(x) for x in xs]
+    aitems = [dict(**{"in": o}, out=a, n=n, in_bytes=int(b.item()), dtype=gz.GZ_F32, block_len=L)
+              for o, a, n, b in zip(outs, accs, ns, nbs)]
+    ctx.batch(gz.GZ_OP_ACCUMULATE, ctx.requests(aitems), threads=64)
+    torch.cuda.synchronize()
+    for w, a, x in zip(want, accs, xs):
+        assert a.cpu().numpy().tobytes() == (oracle.decompress(w) + x).tobytes()
     assert_ok(ctx)
     mixed = dict(items[0])
     mixed["n"] = 3 * 4096

@@ -50,7 +50,7 @@ def stream_with_specials(n, L, seed):
 
 
 @pytest.mark.parametrize("L", [32, 64, 128])
-@pytest.mark.parametrize("tpb", [128, 256, 512, 1024])
+@pytest.mark.parametrize("tpb", [0, 64, 128, 256, 512, 1024])   # 0 default, 64 per-wave
 def test_decompress_add_matches_oracle(ctx, oracle, L, tpb):
     import torch
     say("decompress_add", L, tpb)
@@ -114,14 +114,16 @@ def test_batched_accumulate_plan(ctx, oracle, gz):
     A = [dev(a) for a in accs]
     items = [{"in": S[i], "out": A[i], "n": ns[i], "in_bytes": ss[i].size,
               "dtype": gz.GZ_F32, "block_len": Ls[i]} for i in range(len(ns))]
-    plan = ctx.plan(gz.GZ_OP_ACCUMULATE, ctx.requests(items))
-    for rep in range(2):  # the second launch adds the streams again
-        plan.launch()
-        torch.cuda.synchronize()
-        for i in range(len(ns)):
-            want = co.decompress_add(ss[i], accs[i])
-            assert A[i].cpu().numpy().tobytes() == want.tobytes(), (rep, i)
-            accs[i] = want
+    for tpb in (0, 64, 512):  # default (strips), per-wave, strips
+        plan = ctx.plan(gz.GZ_OP_ACCUMULATE, ctx.requests(items), threads=tpb)
+        for rep in range(2):  # the second launch adds the streams again
+            plan.launch()
+            torch.cuda.synchronize()
+            for i in range(len(ns)):
+                want = co.decompress_add(ss[i], accs[i])
+                assert A[i].cpu().numpy().tobytes() == want.tobytes(), (tpb, rep, i)
+                accs[i] = want
+        plan.close()
     assert ctx.device_status() == 0
 
 
