@@ -139,6 +139,15 @@ gz_status gz_ctx_status(gz_ctx* ctx, gz_stream_t stream, gz_status* device_statu
 /* Clears the context's look-back and ticket state (after a device error). */
 gz_status gz_ctx_reset(gz_ctx* ctx, gz_stream_t stream);
 
+/* Bound of every wait between workgroups or waves of one launch (the
+ * look-back of Sec. 3.3.4's offset scan, the per-wave encoder's rounds), in
+ * microseconds of the device's constant-rate clock; default one second.  A
+ * wait that expires sets GZ_ETIMEOUT in the device status (the stream being
+ * written is then invalid) and its kernel finishes instead of waiting on.
+ * 0 is allowed: a test of that path.  Plans read the bound at each launch;
+ * a captured graph keeps the one it was captured with.  Host only. */
+gz_status gz_ctx_set_wait(gz_ctx* ctx, uint64_t usec);
+
 /* Largest stream a compression of n elements can produce:
  * 64 + 4*ceil(n/4096) + roundup4(ceil(n/L)) + n*sizeof(T); 0 for an invalid
  * dtype or block length.  Compressed sizes are known only after the kernel

@@ -88,7 +88,8 @@ struct gz_ctx {
   Tuned tuned[3][2][3];  // single calls: [op][dtype][log2L-5]
   Tuned batch_tuned[4][2];  // batched launches: [op][batch holds fp64]
   uint32_t best_L[2] = {0, 0};  // tuned block length per dtype (0: untuned, 32)
-  uint64_t wait_ticks = 0;    // one second of the device's constant-rate clock
+  uint64_t wait_ticks = 0;    // wait bound in ticks of the constant-rate clock (1 s default)
+  uint64_t wclk_khz = 0;      // that clock's rate
   float* train_ws = nullptr;  // selector training: per-sample backward terms
   // plan arena: descriptors and strip maps of live plans (allocated once)
   Job* plan_jobs = nullptr;
@@ -501,6 +502,7 @@ gz_status gz_ctx_create(gz_ctx** out, int device, uint64_t max_elems, uint32_t m
   if (hipDeviceGetAttribute(&wclk_khz, hipDeviceAttributeWallClockRate, device) != hipSuccess ||
       wclk_khz <= 0)
     wclk_khz = 100000;
+  c->wclk_khz = (uint64_t)wclk_khz;
   c->wait_ticks = (uint64_t)wclk_khz * 1000ull;
   int lds = 0;
   if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess ||
@@ -592,6 +594,12 @@ gz_status gz_ctx_status(gz_ctx* c, gz_stream_t stream, gz_status* dev) {
 gz_status gz_ctx_reset(gz_ctx* c, gz_stream_t stream) {
   if (!c) return GZ_EINVAL;
   return hip_status(gzk::launch_reset(c->ctl(), (hipStream_t)stream));
+}
+
+gz_status gz_ctx_set_wait(gz_ctx* c, uint64_t usec) {
+  if (!c || usec > (1ull << 40)) return GZ_EINVAL;
+  c->wait_ticks = usec * c->wclk_khz / 1000ull;
+  return GZ_OK;
 }
 
 gz_status gz_quantize(gz_ctx* c, const void* d_in, uint64_t n, gz_dtype dtype, double eb,

@@ -46,6 +46,7 @@ _SIGS = {
     "gz_ctx_destroy": ([_vp], None),
     "gz_ctx_status": ([_vp, _vp, ctypes.POINTER(_i32)], _i32),
     "gz_ctx_reset": ([_vp, _vp], _i32),
+    "gz_ctx_set_wait": ([_vp, _u64], _i32),
     "gz_compress_bound": ([_u64, _i32, _u32], _u64),
     "gz_quantize": ([_vp, _vp, _u64, _i32, _dbl, _vp, _vp, _vp], _i32),
     "gz_compress": ([_vp, _vp, _u64, _i32, _dbl, _pp, _vp, _u64, _vp, _vp], _i32),
@@ -184,6 +185,16 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def reset(self, stream=None):
+        """Clears the context's look-back and ticket state (after a device
+        error such as an expired wait)."""
+        check(gz_ctx_reset(self.h, _stream(stream)), "gz_ctx_reset")
+
+    def set_wait(self, usec):
+        """Bound of the kernels' waits between waves, in microseconds
+        (default 1 s); an expired wait reports GZ_ETIMEOUT."""
+        check(gz_ctx_set_wait(self.h, int(usec)), "gz_ctx_set_wait")
 
     def device_status(self, stream=None):
         """Waits for `stream` (default: the current one) and returns and
