@@ -2190,9 +2190,28 @@ __device__ __forceinline__ void wave_encode_unit(const Job& J, uint64_t u, uint3
         const uint32_t P = whole ? Ptot : (h ? Ptot - wb.half0 : wb.half0);
         S = wave_stage_payload<SUPER, false>(fs.pay + wb.E + hoff, P, X);
       }
-      // the addend's loads are in flight during the decode
+      // the lane's own 32 addend values, in flight during the decode
       u4u lr[8];
-      wave_half_load((const uint32_t*)(J.local + e0 + h * HALF), hval, lr);
+      {
+        const uint32_t* src = (const uint32_t*)(J.local + e0 + h * HALF) + 32 * lane;
+        const uint32_t vdw = vcnt;
+#pragma unroll
+        for (uint32_t k = 0; k < 8; ++k) {
+          if (FULL) {
+            lr[k] = ((const u4u*)src)[k];
+          } else {
+            const uint32_t dw = 4 * k;
+            if (dw + 4 <= vdw) {
+              lr[k] = *(const u4u*)(src + dw);
+            } else {
+              lr[k].x = dw + 0 < vdw ? src[dw + 0] : 0u;
+              lr[k].y = dw + 1 < vdw ? src[dw + 1] : 0u;
+              lr[k].z = dw + 2 < vdw ? src[dw + 2] : 0u;
+              lr[k].w = 0u;
+            }
+          }
+        }
+      }
       if (good) {
         wave_lds_sync();
         unpack_seg<float, LPB, FULL>(S + (wb.boff[h] - hoff), wb.kind[h], wb.F[h], w, vcnt,
@@ -2207,13 +2226,14 @@ __device__ __forceinline__ void wave_encode_unit(const Job& J, uint64_t u, uint3
         fs.di.kind = K_ZERO;
         fs.di.F = 0;
       }
-      wave_lds_sync();  // payload words read before X takes the second addend
-      wave_regs_to_x(lr, AD);
-      wave_lds_sync();
-      float a[32];
-      wave_row_get(AD, a);
+      wave_lds_sync();  // payload words read before X takes the sums
 #pragma unroll
-      for (int i = 0; i < 32; ++i) v[i] = v[i] + a[i];  // incoming + local, fp32
+      for (int k = 0; k < 8; ++k) {  // incoming + local, fp32
+        v[4 * k] = v[4 * k] + __uint_as_float(lr[k].x);
+        v[4 * k + 1] = v[4 * k + 1] + __uint_as_float(lr[k].y);
+        v[4 * k + 2] = v[4 * k + 2] + __uint_as_float(lr[k].z);
+        v[4 * k + 3] = v[4 * k + 3] + __uint_as_float(lr[k].w);
+      }
       wave_row_put(AD, v);  // the sums, for a RAW block (own row)
     } else {
       // the first half's loads were issued by the caller (pre); the second
