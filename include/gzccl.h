@@ -241,10 +241,12 @@ gz_status gz_scatter_decompress(gz_ctx* ctx, const void* d_packed,
  * cost") share one grid.  op selects compress, decompress, fused step or
  * decode-and-accumulate (fp32 only, as gz_decompress_add); p gives
  * threads/grid only (0: the shapes gz_tune_batch stored for this op and
- * element-type mix, else defaults).  A compress or fused batch whose jobs
- * are all fp32 with the same block length and superblock count can run on
- * the per-wave kernels (threads 64; refused with GZ_EUNSUPPORTED for other
- * batches); a fused batch does by default. */
+ * element-type mix, else defaults).  threads 64 selects the per-wave
+ * kernels: for any decompress or decode-and-accumulate batch whose jobs
+ * each hold at least one element, and for a compress or fused batch whose
+ * jobs are all fp32 with the same block length and superblock count
+ * (GZ_EUNSUPPORTED for other batches).  By default decompress and fused
+ * batches run on them where they can. */
 gz_status gz_batch(gz_ctx* ctx, gz_op op, const gz_request* h_reqs,
                    uint32_t nreq, const gz_params* p, gz_stream_t stream);
 
