@@ -2045,8 +2045,9 @@ __attribute__((amdgpu_waves_per_eu(WIDE ? 1 : 2, 2))) void k_batch_decode_w(
 // Wave region (dwords): X and A, each 64 padded segments, and HB, the
 // superblock's header bytes.  Compression: input values through X, first
 // half's payload in A, second half's in X.  Fused step: the incoming payload
-// staged in X (whole, or half by half if it does not fit), the first half's
-// addend and then payload in A, the second half's addend and payload in X.
+// staged in X (whole, or half by half if it does not fit); each lane loads
+// its own addend row; the first half's sums (kept for RAW blocks) and then
+// payload in A, the second half's sums and payload in X.
 struct WaveEnc {
   static constexpr uint32_t WAVES = 8;  // per workgroup
   static constexpr uint32_t STR = 36;   // seg_stride<float>()
@@ -2073,6 +2074,29 @@ __device__ __forceinline__ void wave_half_load(const uint32_t* src, uint32_t hva
       r[u].y = dw + 1 < hval ? src[dw + 1] : 0u;
       r[u].z = dw + 2 < hval ? src[dw + 2] : 0u;
       r[u].w = 0u;
+    }
+  }
+}
+
+// The lane's own row of 32 values at src (vcnt valid, the rest 0): eight
+// 16-byte loads, each instruction touching a line per lane, nearly all L1
+// hits after the first.
+template <bool FULL>
+__device__ __forceinline__ void wave_row_load(const uint32_t* src, uint32_t vcnt, u4u (&r)[8]) {
+#pragma unroll
+  for (uint32_t k = 0; k < 8; ++k) {
+    if (FULL) {
+      r[k] = ((const u4u*)src)[k];
+    } else {
+      const uint32_t dw = 4 * k;
+      if (dw + 4 <= vcnt) {
+        r[k] = *(const u4u*)(src + dw);
+      } else {
+        r[k].x = dw + 0 < vcnt ? src[dw + 0] : 0u;
+        r[k].y = dw + 1 < vcnt ? src[dw + 1] : 0u;
+        r[k].z = dw + 2 < vcnt ? src[dw + 2] : 0u;
+        r[k].w = 0u;
+      }
     }
   }
 }
@@ -2184,34 +2208,16 @@ __device__ __forceinline__ void wave_encode_unit(const Job& J, uint64_t u, uint3
     const uint32_t vcnt = FULL ? 32u : (uint32_t)min(32, max(0, (int)hval - 32 * (int)lane));
     float v[32];
     if (FUSED) {
-      uint32_t* AD = h ? X : A;  // the addend's transpose, then the sums
+      uint32_t* AD = h ? X : A;  // the sums' rows
       const uint32_t hoff = (h && !whole) ? wb.half0 : 0u;
       if (good && (h == 0 || !whole)) {
         const uint32_t P = whole ? Ptot : (h ? Ptot - wb.half0 : wb.half0);
         S = wave_stage_payload<SUPER, false>(fs.pay + wb.E + hoff, P, X);
       }
-      // the lane's own 32 addend values, in flight during the decode
+      // the lane's own 32 addend values, in flight during the decode (a
+      // coalesced load transposed through LDS measured slower here)
       u4u lr[8];
-      {
-        const uint32_t* src = (const uint32_t*)(J.local + e0 + h * HALF) + 32 * lane;
-        const uint32_t vdw = vcnt;
-#pragma unroll
-        for (uint32_t k = 0; k < 8; ++k) {
-          if (FULL) {
-            lr[k] = ((const u4u*)src)[k];
-          } else {
-            const uint32_t dw = 4 * k;
-            if (dw + 4 <= vdw) {
-              lr[k] = *(const u4u*)(src + dw);
-            } else {
-              lr[k].x = dw + 0 < vdw ? src[dw + 0] : 0u;
-              lr[k].y = dw + 1 < vdw ? src[dw + 1] : 0u;
-              lr[k].z = dw + 2 < vdw ? src[dw + 2] : 0u;
-              lr[k].w = 0u;
-            }
-          }
-        }
-      }
+      wave_row_load<FULL>((const uint32_t*)(J.local + e0 + h * HALF) + 32 * lane, vcnt, lr);
       if (good) {
         wave_lds_sync();
         unpack_seg<float, LPB, FULL>(S + (wb.boff[h] - hoff), wb.kind[h], wb.F[h], w, vcnt,
