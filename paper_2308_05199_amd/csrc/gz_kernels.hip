@@ -271,14 +271,15 @@ __device__ __forceinline__ bool aborted(const Ctl& C) {
 }
 
 // Bound of every inter-workgroup wait: C.wait_ticks of the constant-rate
-// clock from the first unsuccessful poll (or SPIN_LIMIT polls), or another
-// workgroup's timeout.  Checked every 64 polls.
+// clock from the 64th unsuccessful poll (or SPIN_LIMIT polls), or another
+// workgroup's timeout.  Checked every 64 polls; the clock (a scalar memory
+// read) is not touched by waits that end within the first 63 polls.
 __device__ __forceinline__ bool wait_over(const Ctl& C, uint32_t spins, uint64_t& t0) {
-  if (spins == 1) {
+  if ((spins & 63u) != 0) return false;
+  if (spins == 64) {
     t0 = (uint64_t)wall_clock64();
     return false;
   }
-  if ((spins & 63u) != 0) return false;
   return spins > SPIN_LIMIT || (uint64_t)wall_clock64() - t0 > C.wait_ticks || aborted(C);
 }
 
