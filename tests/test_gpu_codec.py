@@ -594,3 +594,45 @@ def test_fused_corrupt_stream_sets_status(ctx, oracle, gz, corrupt, tpb):
     assert out[:int(nb.item())].cpu().numpy().tobytes() == \
         oracle.fused_step(s, loc, 1e-4).tobytes()
     assert_ok(ctx)
+
+
+def test_per_wave_encoders_repeat_bit_identical(ctx, oracle, gz):
+    """The per-wave encoders' offsets come from a two-level scan whose waits
+    resolve in a different order on every launch: 40 launches of a fused
+    plan and of a compression plan (8 ragged chunks, per-wave kernels) must
+    each write the oracle's bytes every time."""
+    import torch
+    say("per-wave repeats")
+    ns = [(1 << 20) + 3333] * 8
+    eb = 1e-4
+    xs, ins, outs, nbs, items, cap = _uniform_batch(gz, ns, eb, 32, 60)
+    want = [oracle.compress(x, eb) for x in xs]
+    g = np.random.default_rng(61)
+    locs = [g.normal(0, 0.3, n).astype(np.float32) for n in ns]
+    want_f = [oracle.fused_step(w, l, eb) for w, l in zip(want, locs)]
+    cplan = ctx.plan(gz.GZ_OP_COMPRESS, ctx.requests(items), threads=64)
+    cplan.launch()
+    torch.cuda.synchronize()
+    fo = [torch.zeros(cap, dtype=torch.uint8, device="cuda") for _ in ns]
+    fb = [torch.zeros(1, dtype=torch.int64, device="cuda") for _ in ns]
+    fitems = [dict(**{"in": o}, local=dev(l), out=f, out_bytes=b, n=n, in_bytes=cap,
+                   out_cap=cap, eb=eb, dtype=gz.GZ_F32, block_len=32)
+              for o, l, f, b, n in zip(outs, locs, fo, fb, ns)]
+    fplan = ctx.plan(gz.GZ_OP_FUSED, ctx.requests(fitems), threads=64)
+    for rep in range(40):
+        for f in fo:
+            f.zero_()
+        fplan.launch()
+        torch.cuda.synchronize()
+        for w, f, b in zip(want_f, fo, fb):
+            assert f[:int(b.item())].cpu().numpy().tobytes() == w.tobytes(), rep
+    for rep in range(40):
+        for o in outs:
+            o.zero_()
+        cplan.launch()
+        torch.cuda.synchronize()
+        for w, o, b in zip(want, outs, nbs):
+            assert o[:int(b.item())].cpu().numpy().tobytes() == w.tobytes(), rep
+    cplan.close()
+    fplan.close()
+    assert_ok(ctx)
