@@ -1651,13 +1651,19 @@ __device__ __forceinline__ void wave_lds_sync() {
   asm volatile("" ::: "memory");
 }
 
-// The stream header against the job, by one wave: ok, payload dwords and step.
+// The lane's word of the stream header (lanes 0..15; 0 if unreadable).
+__device__ __forceinline__ uint32_t wave_header_load(const Job& J, const uint8_t* in) {
+  const uint32_t lane = __lane_id();
+  return (lane < 16 && J.in_bytes >= HDR) ? ((const uint32_t*)in)[lane] : 0u;
+}
+
+// The stream header (the lanes' words wv) against the job, by one wave: ok,
+// payload dwords and step.
 template <typename T>
-__device__ __forceinline__ bool wave_header(const Job& J, const uint8_t* in, uint64_t& paydw,
-                                            T& t) {
+__device__ __forceinline__ bool wave_header_eval(const Job& J, uint32_t wv, uint64_t& paydw,
+                                                 T& t) {
   const uint32_t lane = __lane_id();
   const bool readable = J.in_bytes >= HDR;
-  const uint32_t wv = (lane < 16 && readable) ? ((const uint32_t*)in)[lane] : 0u;
   bool ok = true;
   switch (lane) {
     case 0: ok = wv == 0x31435A47u; break;
@@ -1683,6 +1689,12 @@ __device__ __forceinline__ bool wave_header(const Job& J, const uint8_t* in, uin
   paydw = payload / 4;
   t = sizeof(T) == 4 ? (T)t32 : (T)t64;
   return good;
+}
+
+template <typename T>
+__device__ __forceinline__ bool wave_header(const Job& J, const uint8_t* in, uint64_t& paydw,
+                                            T& t) {
+  return wave_header_eval<T>(J, wave_header_load(J, in), paydw, t);
 }
 
 // Block layout of superblock sb of an incoming stream, read by one wave:
@@ -2159,15 +2171,30 @@ __device__ __forceinline__ void wave_pack(const Job& J, uint64_t seg, uint32_t w
   }
 }
 
-// Encodes superblock u of job J (fused: incoming stream J.in plus addend
-// J.local); gs: its look-back word, chain0 the job's first.  nxt: the
-// wave's next ticket, taken once the offset is known.
+// The fused step's first words of a superblock (the incoming stream's
+// header word of the lane, table and header-byte words), loaded ahead.
+struct UnitPre {
+  uint32_t wv, raw[3];
+  bool valid;
+};
+
+template <int L>
+__device__ __forceinline__ void wave_unit_preload(const Job& J, uint64_t u, UnitPre& p) {
+  const uint8_t* in = (const uint8_t*)J.in;
+  wave_blocks_load<L, true>(J, in, u, p.raw);
+  p.wv = wave_header_load(J, in);
+  p.valid = true;
+}
+
 // Encodes superblock u of job J into the wave's region (fused: incoming
-// stream J.in plus addend J.local): tot[0] payload dwords in A, tot[1] in X,
-// header bytes in HB; good is false for a malformed incoming superblock.
-template <int L, bool FUSED, bool FULL>
+// stream J.in plus addend J.local; ahead: its first words if loaded ahead):
+// tot[0] payload dwords in A, tot[1] in X, header bytes in HB; good is false
+// for a malformed incoming superblock.  pub(size) is called with the whole
+// size as soon as it is known, before the second half is packed.
+template <int L, bool FUSED, bool FULL, class Pub>
 __device__ __forceinline__ void wave_encode_unit(const Job& J, uint64_t u, uint32_t* R,
-                                                 uint32_t (&tot)[2], bool& good) {
+                                                 uint32_t (&tot)[2], bool& good,
+                                                 const UnitPre& ahead, const Pub& pub) {
   constexpr uint32_t LPB = L / 32, BPS = SUPER / L, HALF = 64 * SEG;
   const uint32_t lane = __lane_id();
   const uint32_t w = lane & (LPB - 1);
@@ -2190,10 +2217,10 @@ __device__ __forceinline__ void wave_encode_unit(const Job& J, uint64_t u, uint3
   fs.t = 0.0f;
   if (FUSED) {
     uint64_t paydw = 0;
-    uint32_t raw[3];
-    wave_blocks_load<L, true>(J, in, u, raw);  // in flight with the header's words
-    good = wave_header<float>(J, in, paydw, fs.t);
-    if (good) good = wave_blocks_eval<float, L>(J, u, paydw, nval, raw, wb);
+    UnitPre p = ahead;
+    if (!p.valid) wave_unit_preload<L>(J, u, p);  // table words with the header's
+    good = wave_header_eval<float>(J, p.wv, paydw, fs.t);
+    if (good) good = wave_blocks_eval<float, L>(J, u, paydw, nval, p.raw, wb);
   }
   // the whole incoming payload is staged at once when its realigned copy
   // fits X (always, at any ratio above about 1.8)
@@ -2261,6 +2288,7 @@ __device__ __forceinline__ void wave_encode_unit(const Job& J, uint64_t u, uint3
     const uint32_t incl = wave_incl_scan(contrib);
     const uint32_t boff = w == 0 ? incl - contrib : incl - lc.size_dw;
     tot[h] = __shfl(incl, 63);
+    if (h == 1) pub(tot[0] + tot[1]);
     if (w == 0)
       ((uint8_t*)HB)[(64 * h + lane) / LPB] =
           (uint8_t)(lc.exists ? ((lc.kind << 5) | lc.F) : 0u);
@@ -2380,9 +2408,33 @@ __device__ __forceinline__ bool lds_wait_ge(const Ctl& C, const uint32_t* p, uin
 
 struct Claim {
   uint32_t round, slot, ticket;  // ticket 0xFFFFFFFF: timed out
+  bool done;                     // ticket known
 };
 
-__device__ __forceinline__ Claim wave_claim(const Ctl& C, WaveSched& ws) {
+// A round's first claimer opens it: resets the entry, takes the round's
+// ticket (handed on, or, for round 0, from the counter) and marks it ready.
+__device__ __forceinline__ uint32_t wave_round_open(const Ctl& C, RoundState& rs,
+                                                    uint32_t round) {
+  uint32_t t = 0;
+  if (__lane_id() == 0) {
+    rs.cnt = 0;
+    rs.fetch = 0;
+    rs.pready = 0;
+    rs.released = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < WaveEnc::WAVES; ++i) rs.size[i] = SIZE_NONE;
+    t = round > 0 ? rs.pticket : atomicAdd(&C.ctrl->ticket, 1u);
+    rs.ticket = t;
+    lds_store_rel(&rs.ready, round + 1);
+  }
+  return __builtin_amdgcn_readfirstlane(__shfl(t, 0));
+}
+
+// Takes the wave's next slot and, if that needs no wait, its round's ticket
+// (done); wave_claim_finish completes it otherwise.  A wave may try this
+// before releasing its current slot (it waits for nothing), but finishes
+// only after the release, so the claim protocol's waits are unchanged.
+__device__ __forceinline__ Claim wave_claim_try(const Ctl& C, WaveSched& ws) {
   const uint32_t lane = __lane_id();
   uint32_t k = 0;
   if (lane == 0) k = atomicAdd(&ws.claim, 1u);
@@ -2390,38 +2442,43 @@ __device__ __forceinline__ Claim wave_claim(const Ctl& C, WaveSched& ws) {
   Claim c;
   c.round = k / WaveEnc::WAVES;
   c.slot = k % WaveEnc::WAVES;
+  c.ticket = 0xFFFFFFFFu;
+  c.done = false;
+  RoundState& rs = ws.rs[c.round % RING];
+  uint32_t ok = 0;
+  if (lane == 0)
+    ok = c.slot == 0
+             ? (lds_load_acq(&rs.released) >= WaveEnc::WAVES &&
+                (c.round == 0 || lds_load_acq(&rs.pflag) >= c.round + 1))
+             : lds_load_acq(&rs.ready) >= c.round + 1;
+  if (__shfl(ok, 0)) {
+    c.ticket = c.slot == 0 ? wave_round_open(C, rs, c.round)
+                           : __builtin_amdgcn_readfirstlane(rs.ticket);
+    c.done = true;
+  }
+  return c;
+}
+
+__device__ __forceinline__ void wave_claim_finish(const Ctl& C, WaveSched& ws, Claim& c) {
+  if (c.done) return;
+  c.done = true;
   RoundState& rs = ws.rs[c.round % RING];
   if (c.slot == 0) {
-    // the entry's previous round has been released by all its claimers
-    if (!lds_wait_ge(C, &rs.released, WaveEnc::WAVES)) {
-      c.ticket = 0xFFFFFFFFu;
-      return c;
-    }
-    // the round's ticket, handed on by the previous round
-    if (c.round > 0 && !lds_wait_ge(C, &rs.pflag, c.round + 1)) {
-      c.ticket = 0xFFFFFFFFu;
-      return c;
-    }
-    uint32_t t = 0;
-    if (lane == 0) {
-      rs.cnt = 0;
-      rs.fetch = 0;
-      rs.pready = 0;
-      rs.released = 0;
-#pragma unroll
-      for (uint32_t i = 0; i < WaveEnc::WAVES; ++i) rs.size[i] = SIZE_NONE;
-      t = c.round > 0 ? rs.pticket : atomicAdd(&C.ctrl->ticket, 1u);
-      rs.ticket = t;
-      lds_store_rel(&rs.ready, c.round + 1);
-    }
-    c.ticket = __builtin_amdgcn_readfirstlane(__shfl(t, 0));
-    return c;
+    // the entry's previous round has been released by all its claimers, and
+    // the round's ticket has been handed on by the previous round
+    if (!lds_wait_ge(C, &rs.released, WaveEnc::WAVES) ||
+        (c.round > 0 && !lds_wait_ge(C, &rs.pflag, c.round + 1)))
+      return;  // timed out: ticket stays past the end
+    c.ticket = wave_round_open(C, rs, c.round);
+    return;
   }
-  if (!lds_wait_ge(C, &rs.ready, c.round + 1)) {
-    c.ticket = 0xFFFFFFFFu;
-    return c;
-  }
+  if (!lds_wait_ge(C, &rs.ready, c.round + 1)) return;
   c.ticket = __builtin_amdgcn_readfirstlane(rs.ticket);
+}
+
+__device__ __forceinline__ Claim wave_claim(const Ctl& C, WaveSched& ws) {
+  Claim c = wave_claim_try(C, ws);
+  wave_claim_finish(C, ws, c);
   return c;
 }
 
@@ -2447,23 +2504,25 @@ __device__ __forceinline__ uint32_t round_sum(const RoundState& rs) {
 }
 
 // Superblock u (slot cl.slot of round entry rs; u >= J.NS: an empty slot
-// past the job's end) of round gs of the chain that starts at chain0.
+// past the job's end) of round gs of the chain that starts at chain0:
+// encodes it into the wave's region and finds its offset (off, dwords).
+// True if the unit is to be written out (wave_write_unit); the caller then
+// releases the slot.
 template <int L, bool FUSED>
-__device__ __forceinline__ void wave_round_unit(const Job& J, uint64_t u, const Claim& cl,
-                                                WaveSched& ws, uint64_t gs, uint64_t chain0,
-                                                const Ctl& C, uint32_t ep, uint32_t* R) {
+__device__ __forceinline__ bool wave_round_begin(const Job& J, uint64_t u, const Claim& cl,
+                                                 WaveSched& ws, uint64_t gs, uint64_t chain0,
+                                                 const Ctl& C, uint32_t ep, uint32_t* R,
+                                                 const UnitPre& pre, uint32_t (&tot)[2],
+                                                 uint64_t& off) {
   RoundState& rs = ws.rs[cl.round % RING];
   const uint32_t lane = __lane_id();
   const bool live = u < J.NS;
-  uint32_t tot[2] = {0u, 0u};
+  tot[0] = tot[1] = 0u;
   bool good = true;
-  if (live) {
-    if ((u + 1) * SUPER <= J.n) wave_encode_unit<L, FUSED, true>(J, u, R, tot, good);
-    else wave_encode_unit<L, FUSED, false>(J, u, R, tot, good);
-  }
   // the size into the round; the wave completing the count publishes
-  if (lane == 0) {
-    __hip_atomic_store(&rs.size[cl.slot], tot[0] + tot[1], __ATOMIC_RELEASE,
+  auto pub = [&](uint32_t size) {
+    if (lane != 0) return;
+    __hip_atomic_store(&rs.size[cl.slot], size, __ATOMIC_RELEASE,
                        __HIP_MEMORY_SCOPE_WORKGROUP);
     const uint32_t c =
         __hip_atomic_fetch_add(&rs.cnt, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP) + 1;
@@ -2478,10 +2537,13 @@ __device__ __forceinline__ void wave_round_unit(const Job& J, uint64_t u, const 
           st_agent(C.status + gs, sw_pack(2, ep, rs.prefix + agg));
       }
     }
-  }
-  if (!live) {
-    wave_release(rs);
-    return;
+  };
+  if (live) {
+    if ((u + 1) * SUPER <= J.n) wave_encode_unit<L, FUSED, true>(J, u, R, tot, good, pre, pub);
+    else wave_encode_unit<L, FUSED, false>(J, u, R, tot, good, pre, pub);
+  } else {
+    pub(0u);
+    return false;
   }
   // the round's prefix: fetched by one wave, read by the others
   uint32_t fetcher = 0;
@@ -2524,8 +2586,8 @@ __device__ __forceinline__ void wave_round_unit(const Job& J, uint64_t u, const 
     if (to) atomicOr(&C.ctrl->err, ERRF_TIMEOUT);
     if (!good) atomicOr(&C.ctrl->err, ERRF_CORRUPT);
   }
-  if (!to && good) wave_write_unit<L>(J, u, prefix + below, tot, R);
-  wave_release(rs);
+  off = prefix + below;
+  return !to && good;
 }
 
 #define GZ_WAVE_ATTR __launch_bounds__(WaveEnc::WAVES * 64) __attribute__((amdgpu_waves_per_eu(2, 2)))
@@ -2543,16 +2605,31 @@ __global__ GZ_WAVE_ATTR void k_encode_w(Job J, Ctl C) {
   uint32_t* R = g_stage + (threadIdx.x >> 6) * WaveEnc::REGION;
   const uint32_t ep = ld_agent32(&C.ctrl->epoch);
   const uint64_t NR = rounds_of(J.NS);
+  Claim cl = wave_claim(C, ws);
+  UnitPre pre;
+  pre.valid = false;
   for (;;) {
-    const Claim cl = wave_claim(C, ws);
     RoundState& rs = ws.rs[cl.round % RING];
     if (cl.ticket >= NR) {  // past the end (or timed out)
       if (cl.slot == 0 && __lane_id() == 0) wave_hand_on(C, ws, cl.round, cl.ticket, false);
       wave_release(rs);
       break;
     }
-    wave_round_unit<L, FUSED>(J, (uint64_t)cl.ticket * WaveEnc::WAVES + cl.slot, cl, ws,
-                              cl.ticket, 0, C, ep, R);
+    const uint64_t u = (uint64_t)cl.ticket * WaveEnc::WAVES + cl.slot;
+    uint32_t tot[2];
+    uint64_t off = 0;
+    const bool wr = wave_round_begin<L, FUSED>(J, u, cl, ws, cl.ticket, 0, C, ep, R, pre, tot, off);
+    // the next slot, and its first words ahead of this unit's stores
+    Claim nx = wave_claim_try(C, ws);
+    pre.valid = false;
+    if (FUSED && nx.done && nx.ticket < NR) {
+      const uint64_t v = (uint64_t)nx.ticket * WaveEnc::WAVES + nx.slot;
+      if (v < J.NS) wave_unit_preload<L>(J, v, pre);
+    }
+    if (wr) wave_write_unit<L>(J, u, off, tot, R);
+    wave_release(rs);
+    wave_claim_finish(C, ws, nx);
+    cl = nx;
   }
   epilogue(C);
 }
@@ -2566,8 +2643,10 @@ __global__ GZ_WAVE_ATTR void k_batch_encode_w(const Job* __restrict__ jobs, uint
   wave_sched_init(ws);
   uint32_t* R = g_stage + (threadIdx.x >> 6) * WaveEnc::REGION;
   const uint32_t ep = ld_agent32(&C.ctrl->epoch);
+  Claim cl = wave_claim(C, ws);
+  UnitPre pre;
+  pre.valid = false;
   for (;;) {
-    const Claim cl = wave_claim(C, ws);
     RoundState& rs = ws.rs[cl.round % RING];
     if (cl.ticket >= total) {  // past the end (or timed out)
       if (cl.slot == 0 && __lane_id() == 0) wave_hand_on(C, ws, cl.round, cl.ticket, false);
@@ -2577,8 +2656,23 @@ __global__ GZ_WAVE_ATTR void k_batch_encode_w(const Job* __restrict__ jobs, uint
     const uint32_t j = cl.ticket % njobs;
     const Job J = jobs[j];
     const uint64_t NR = rounds_of(J.NS), r = cl.ticket / njobs;
-    wave_round_unit<L, FUSED>(J, r * WaveEnc::WAVES + cl.slot, cl, ws, j * NR + r, j * NR, C,
-                              ep, R);
+    const uint64_t u = r * WaveEnc::WAVES + cl.slot;
+    uint32_t tot[2];
+    uint64_t off = 0;
+    const bool wr =
+        wave_round_begin<L, FUSED>(J, u, cl, ws, j * NR + r, j * NR, C, ep, R, pre, tot, off);
+    // the next slot, and its first words ahead of this unit's stores
+    Claim nx = wave_claim_try(C, ws);
+    pre.valid = false;
+    if (FUSED && nx.done && nx.ticket < total) {
+      const Job& K = jobs[nx.ticket % njobs];
+      const uint64_t v = (uint64_t)(nx.ticket / njobs) * WaveEnc::WAVES + nx.slot;
+      if (v < K.NS) wave_unit_preload<L>(K, v, pre);
+    }
+    if (wr) wave_write_unit<L>(J, u, off, tot, R);
+    wave_release(rs);
+    wave_claim_finish(C, ws, nx);
+    cl = nx;
   }
   epilogue(C);
 }
