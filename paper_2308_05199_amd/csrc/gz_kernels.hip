@@ -1849,12 +1849,84 @@ __device__ __forceinline__ const uint32_t* wave_stage_payload(const uint32_t* sr
 // malformed.  raw: sb's table and header-byte words (wave_blocks_load), on
 // return those of the wave's next superblock nsb (if it exists), whose
 // loads go out with this superblock's payload copy.
+// wave_stage_payload in two parts, so that a superblock's payload is in
+// flight while the wave decodes the previous one.  Issue: the first 512
+// chunks (8 per lane) and the partial last chunk's dwords into registers,
+// every load issued whatever the size (clamped to the readable bytes
+// [16-byte floor of src, src + P), or to the stream header's first aligned
+// chunk if that range is empty), so that each path issues the same memory
+// operations.  Commit: those into dst, and any chunks past the first 512
+// (payloads over 2048 dwords) copied there and then.
+// The stream header's first 16-byte aligned chunk (always readable once the
+// header has been checked).
+__device__ __forceinline__ const uint32_t* hdr_chunk(const uint8_t* in) {
+  return (const uint32_t*)(in + ((0u - (uint32_t)(uintptr_t)in) & 15u));  // keeps in's address space
+}
+
+struct PayRegs {
+  u4u r[8];
+  uint32_t t[3];
+  const u4u* al;
+  uint32_t delta, full, nch, P;
+};
+
+__device__ __forceinline__ void wave_pay_issue(const uint32_t* src, uint32_t P, const uint8_t* in,
+                                               PayRegs& pr) {
+  const uint32_t lane = __lane_id();
+  pr.delta = (uint32_t)(((uintptr_t)src & 15u) >> 2);
+  pr.al = (const u4u*)(src - pr.delta);
+  pr.P = P;
+  pr.full = (pr.delta + P) / 4;
+  pr.nch = (pr.delta + P + 3) / 4;
+  const u4u* safe = (const u4u*)hdr_chunk(in);
+  const u4u* base = pr.full ? pr.al : safe;
+  const uint32_t last = pr.full ? pr.full - 1 : 0u;
+#pragma unroll
+  for (uint32_t u = 0; u < 8; ++u) pr.r[u] = base[min(u * 64 + lane, last)];
+  const uint32_t nd = pr.delta + P;  // readable dwords from al
+  const uint32_t* b32 = nd ? (const uint32_t*)pr.al : (const uint32_t*)safe;
+  const uint32_t lastd = nd ? nd - 1 : 0u;
+#pragma unroll
+  for (uint32_t j = 0; j < 3; ++j) pr.t[j] = b32[min(4 * pr.full + j, lastd)];
+}
+
+// Returns where src[0] landed in dst (16-byte aligned LDS).
+__device__ __forceinline__ const uint32_t* wave_pay_commit(const PayRegs& pr, uint32_t* dst) {
+  const uint32_t lane = __lane_id();
+  u4u* d4 = (u4u*)dst;
+#pragma unroll
+  for (uint32_t u = 0; u < 8; ++u)
+    if (u * 64 + lane < pr.full) d4[u * 64 + lane] = pr.r[u];
+  if (pr.full < pr.nch && lane == 0) {
+    const uint32_t lim = pr.delta + pr.P - 4 * pr.full;  // 1..3 valid dwords
+    u4u r;
+    r.x = pr.t[0];
+    r.y = lim > 1 ? pr.t[1] : 0u;
+    r.z = lim > 2 ? pr.t[2] : 0u;
+    r.w = 0u;
+    d4[pr.full] = r;
+  }
+  for (uint32_t k0 = 8 * 64; k0 < pr.full; k0 += 8 * 64) {
+    u4u r[8];
+#pragma unroll
+    for (uint32_t u = 0; u < 8; ++u) r[u] = pr.al[min(k0 + u * 64 + lane, pr.full - 1)];
+#pragma unroll
+    for (uint32_t u = 0; u < 8; ++u)
+      if (k0 + u * 64 + lane < pr.full) d4[k0 + u * 64 + lane] = r[u];
+  }
+  return dst + pr.delta;
+}
+
+template <typename T, int L, uint32_t OP, uint32_t NOLD>
+__device__ __forceinline__ void wave_unpack_store(const Job& J, uint64_t sb, uint32_t nval, T t,
+                                                  uint32_t* R, const uint32_t* S,
+                                                  const WaveBlocks& wb, const u4u (&old)[NOLD]);
+
 template <typename T, int L, uint32_t OP = 1>
 __device__ bool wave_decode_super(const Job& J, const uint8_t* in, uint64_t sb, uint64_t paydw,
                                   T t, uint32_t* R, uint32_t (&raw)[3], uint64_t nsb) {
   static_assert(OP == 1 || (OP == 3 && sizeof(T) == 4), "accumulation is fp32");
-  constexpr uint32_t EW = sizeof(T) / 4, LPB = L / 32;
-  constexpr uint32_t SEGW = 32 * EW, STR = seg_stride<T>();
+  constexpr uint32_t EW = sizeof(T) / 4;
   constexpr uint32_t CPL = SUPER * EW / 4 / 64;  // 16-byte chunks per lane of a superblock
   const uint32_t lane = __lane_id();
   const uint64_t e0 = sb * SUPER;
@@ -1875,6 +1947,23 @@ __device__ bool wave_decode_super(const Job& J, const uint8_t* in, uint64_t sb, 
   // the next superblock's words are in flight during this one's unpacking
   if (nsb < J.NS) wave_blocks_load<L, false>(J, in, nsb, raw);
   if (!ok) return false;
+  wave_unpack_store<T, L, OP>(J, sb, nval, t, R, S, wb, old);
+  return true;
+}
+
+// Decodes superblock sb (layout wb, payload staged at S in the wave's
+// region R) into J.out (OP 1), or adds it to the fp32 values there (OP 3,
+// old: the accumulator's superblock if whole).
+template <typename T, int L, uint32_t OP, uint32_t NOLD>
+__device__ __forceinline__ void wave_unpack_store(const Job& J, uint64_t sb, uint32_t nval, T t,
+                                                  uint32_t* R, const uint32_t* S,
+                                                  const WaveBlocks& wb, const u4u (&old)[NOLD]) {
+  constexpr uint32_t EW = sizeof(T) / 4, LPB = L / 32;
+  constexpr uint32_t SEGW = 32 * EW, STR = seg_stride<T>();
+  constexpr uint32_t CPL = SUPER * EW / 4 / 64;  // 16-byte chunks per lane of a superblock
+  const uint32_t lane = __lane_id();
+  const uint64_t e0 = sb * SUPER;
+  uint32_t* d32 = (uint32_t*)((T*)J.out + e0);
   wave_lds_sync();
   const uint32_t* boff = wb.boff;
   const uint32_t* kind = wb.kind;
@@ -1947,7 +2036,61 @@ __device__ bool wave_decode_super(const Job& J, const uint8_t* in, uint64_t sb, 
     }
   }
   wave_lds_sync();  // the region is read before the next superblock's copy-in
-  return true;
+}
+
+// One step of wave_decode_whole: commits superblock sb's payload (issued a
+// step earlier), evaluates the layout of the next one (its words loaded a
+// step earlier), issues that payload and the words after it, then decodes
+// and stores sb.
+template <int L>
+__device__ __forceinline__ void wave_whole_step(const Job& J, const uint8_t* in, uint64_t paydw,
+                                                float t, uint32_t* R, uint64_t W, uint64_t NF,
+                                                uint64_t sb, const WaveBlocks& wb, PayRegs& pr,
+                                                uint32_t (&raw)[3], WaveBlocks& wbn, bool& okn) {
+  const uint32_t* pay = (const uint32_t*)(in + J.pay_off);
+  const uint32_t* S = wave_pay_commit(pr, R);
+  const uint64_t nx = min(sb + W, NF - 1);  // past the end: a whole superblock again, unused
+  okn = wave_blocks_eval<float, L>(J, nx, paydw, SUPER, raw, wbn);
+  wave_pay_issue(okn ? pay + wbn.E : hdr_chunk(in), okn ? (uint32_t)(wbn.En - wbn.E) : 0u, in, pr);
+  wave_blocks_load<L, false>(J, in, min(nx + W, NF - 1), raw);
+  const u4u none[1] = {};
+  wave_unpack_store<float, L, 1>(J, sb, SUPER, t, R, S, wb, none);
+}
+
+// The whole superblocks sb, sb + W, ... of an fp32 stream, each one's
+// payload in flight while the wave decodes the one before (the first step
+// is written out once, so that at the loop's head the same memory
+// operations are outstanding on every path: the compiler then waits only
+// for the payload, not for the previous superblock's stores).  On return sb
+// is the wave's first superblock not decoded; bad is set (and decoding
+// stops) at a malformed one.
+template <int L>
+__device__ __forceinline__ void wave_decode_whole(const Job& J, const uint8_t* in, uint64_t paydw,
+                                                  float t, uint32_t* R, uint64_t W, uint64_t& sb,
+                                                  bool& bad) {
+  const uint64_t NF = J.n / SUPER;
+  if (sb >= NF) return;
+  const uint32_t* pay = (const uint32_t*)(in + J.pay_off);
+  uint32_t raw[3];
+  wave_blocks_load<L, false>(J, in, sb, raw);
+  WaveBlocks wb, wbn;
+  bool ok = wave_blocks_eval<float, L>(J, sb, paydw, SUPER, raw, wb), okn;
+  PayRegs pr;
+  wave_pay_issue(ok ? pay + wb.E : hdr_chunk(in), ok ? (uint32_t)(wb.En - wb.E) : 0u, in, pr);
+  wave_blocks_load<L, false>(J, in, min(sb + W, NF - 1), raw);
+  if (!ok) {
+    bad = true;
+    return;
+  }
+  wave_whole_step<L>(J, in, paydw, t, R, W, NF, sb, wb, pr, raw, wbn, okn);
+  for (sb += W; sb < NF; sb += W) {
+    if (!okn) {
+      bad = true;
+      return;
+    }
+    wb = wbn;
+    wave_whole_step<L>(J, in, paydw, t, R, W, NF, sb, wb, pr, raw, wbn, okn);
+  }
 }
 
 template <typename T, int L>
@@ -1961,11 +2104,14 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1, 2))) void k_decompres
   bool bad = !wave_header<T>(J, in, paydw, t);
   if (!bad) {
     const uint64_t W = (uint64_t)gridDim.x * (blockDim.x >> 6);
-    const uint64_t sb0 = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wid;
-    uint32_t raw[3] = {0u, 0u, 0u};
-    if (sb0 < J.NS) wave_blocks_load<L, false>(J, in, sb0, raw);
-    for (uint64_t sb = sb0; sb < J.NS; sb += W)
-      if (!wave_decode_super<T, L>(J, in, sb, paydw, t, R, raw, sb + W)) bad = true;
+    uint64_t sb = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wid;
+    if constexpr (sizeof(T) == 4) wave_decode_whole<L>(J, in, paydw, t, R, W, sb, bad);
+    if (!bad) {  // the rest (fp64: all), one superblock at a time
+      uint32_t raw[3] = {0u, 0u, 0u};
+      if (sb < J.NS) wave_blocks_load<L, false>(J, in, sb, raw);
+      for (; sb < J.NS; sb += W)
+        if (!wave_decode_super<T, L>(J, in, sb, paydw, t, R, raw, sb + W)) bad = true;
+    }
   }
   if (bad && __lane_id() == 0) atomicOr(&C.ctrl->err, ERRF_CORRUPT);
 }
