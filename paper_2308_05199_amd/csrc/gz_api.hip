@@ -112,6 +112,7 @@ struct gz_plan {
   bool wave = false;  // per-wave encoding kernels (total = njobs x rounds)
   bool wave_dec = false;  // per-wave decoding kernels (total = superblocks)
   bool has_map = false;   // wave_dec: d_map lists (job, superblock) pairs
+  uint32_t uni = 0;       // wave_dec: uniform_wave_decode of the jobs
   uint32_t log2L = 5;
 };
 
@@ -336,6 +337,15 @@ uint32_t uniform_jobs(const std::vector<Job>& jobs) {
   for (const Job& J : jobs)
     if (J.nstrips != jobs[0].nstrips) return 0;
   return (uint32_t)jobs.size();
+}
+
+// For a per-wave decoding batch without a map: log2 of the block length when
+// every job is an fp32 1D stream of that block length without a scatter
+// offset (each job then gets waves of its own), else 0.
+uint32_t uniform_wave_decode(const std::vector<Job>& jobs) {
+  for (const Job& J : jobs)
+    if (J.dtype != 0 || J.mode != 0 || J.in_off || J.log2L != jobs[0].log2L) return 0;
+  return jobs.empty() ? 0u : jobs[0].log2L;
 }
 
 // Builds the jobs of a request batch; fills the strip map.
@@ -895,7 +905,7 @@ gz_status gz_scatter_decompress(gz_ctx* c, const void* d_packed, uint64_t packed
       if (r != GZ_OK) return r;
       return hip_status(gzk::launch_decode_wave_batch(
           1, c->d_jobs, smap.empty() ? nullptr : c->d_map, nchunks, (uint32_t)total,
-          dtype == GZ_F64, (uint32_t)c->cus, c->ctl(), st));
+          dtype == GZ_F64, 0u, (uint32_t)c->cus, c->ctl(), st));
     }
     if (p && p->threads == WAVE_TPB) return GZ_EUNSUPPORTED;
   }
@@ -931,7 +941,7 @@ gz_status gz_batch(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t nreq,
       if (r != GZ_OK) return r;
       return hip_status(gzk::launch_decode_wave_batch(
           (uint32_t)op, c->d_jobs, smap.empty() ? nullptr : c->d_map, (uint32_t)jobs.size(),
-          (uint32_t)total, wide, (uint32_t)c->cus, c->ctl(), st));
+          (uint32_t)total, wide, uniform_wave_decode(jobs), (uint32_t)c->cus, c->ctl(), st));
     }
     if (p && p->threads == WAVE_TPB) return GZ_EUNSUPPORTED;
   }
@@ -1009,6 +1019,7 @@ gz_status gz_plan_create(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t
   if (wave_dec) {
     pl->wave_dec = true;
     pl->has_map = !map.empty();
+    pl->uni = uniform_wave_decode(jobs);
     pl->njobs = (uint32_t)jobs.size();
     pl->total = (uint32_t)dec_total;
   }
@@ -1033,7 +1044,7 @@ gz_status gz_plan_launch(gz_plan* pl, gz_stream_t stream) {
   if (pl->wave_dec)
     return hip_status(gzk::launch_decode_wave_batch(
         pl->op, pl->d_jobs, pl->has_map ? pl->d_map : nullptr, pl->njobs, pl->total, pl->wide,
-        (uint32_t)pl->ctx->cus, pl->ctx->ctl(), (hipStream_t)stream));
+        pl->uni, (uint32_t)pl->ctx->cus, pl->ctx->ctl(), (hipStream_t)stream));
   return hip_status(gzk::launch_batch(pl->op, pl->d_jobs, pl->d_map, pl->njobs, pl->total,
                                       pl->ctx->ctl(),
                                       pl->tpb, pl->grid, pl->wide, (hipStream_t)stream));

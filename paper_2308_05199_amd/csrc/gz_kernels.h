@@ -27,10 +27,13 @@ hipError_t launch_accum_wave(const Job& J, const Ctl& C, uint32_t cus, hipStream
 // Per-wave batched decoding (op 1) or decode-and-accumulate (op 3, fp32):
 // total superblocks, superblock i = (d_map[2i], d_map[2i+1]) as (job,
 // superblock), or without a map (jobs of equal superblock counts) superblock
-// i / njobs of job i % njobs.  wide: the batch holds fp64 jobs.
+// i / njobs of job i % njobs.  wide: the batch holds fp64 jobs.  uni (op 1,
+// no map): log2 of the block length if every job is an fp32 1D stream of
+// that block length without a scatter offset (jobs then get waves of their
+// own, each job's whole superblocks decoded as a pipeline), else 0.
 hipError_t launch_decode_wave_batch(uint32_t op, const Job* d_jobs, const uint32_t* d_map,
-                                    uint32_t njobs, uint32_t total, bool wide, uint32_t cus,
-                                    const Ctl& C, hipStream_t st);
+                                    uint32_t njobs, uint32_t total, bool wide, uint32_t uni,
+                                    uint32_t cus, const Ctl& C, hipStream_t st);
 // Per-wave fp32 1D encoding (op 0) or fused step (op 2): every wave encodes
 // whole superblocks, a workgroup's waves the 8 of a round (one chain
 // element).  d_jobs null: the one job J, total = rounds_of(J.NS); else njobs

@@ -2154,22 +2154,65 @@ __device__ __forceinline__ bool wave_batch_super(const Job& J, uint64_t sb, uint
   return wave_decode_super<T, L, OP>(Jl, in, sb, paydw, t, R, raw, ~0ull);
 }
 
+// Superblocks first, first + stride, ... of one fp32 stream (job J, no
+// scatter offset) by one wave, whole ones pipelined as in k_decompress_w.
+template <int L>
+__device__ __forceinline__ void wave_job_decode(const Job& J, uint64_t first, uint64_t stride,
+                                                uint32_t* R, bool& bad) {
+  const uint8_t* in = (const uint8_t*)J.in;
+  uint64_t paydw = 0;
+  float t = 0;
+  if (!wave_header<float>(J, in, paydw, t)) {
+    bad = true;
+    return;
+  }
+  uint64_t sb = first;
+  wave_decode_whole<L>(J, in, paydw, t, R, stride, sb, bad);
+  if (bad) return;
+  uint32_t raw[3] = {0u, 0u, 0u};
+  if (sb < J.NS) wave_blocks_load<L, false>(J, in, sb, raw);
+  for (; sb < J.NS; sb += stride)
+    if (!wave_decode_super<float, L>(J, in, sb, paydw, t, R, raw, sb + stride)) bad = true;
+}
+
 // Batched decoding (OP 1) or decode-and-accumulate (OP 3) by waves: batch
 // superblock i is superblock map[2i + 1] of job map[2i], or, without a map
 // (jobs of equal superblock counts), superblock i / njobs of job i % njobs;
 // waves take them statically.  WIDE: the batch holds fp64 jobs (fp64-sized
-// regions, four waves per workgroup).
+// regions, four waves per workgroup).  uni (decoding without a map): log2
+// of the block length when every job is an fp32 1D stream of that block
+// length without a scatter offset, else 0; then each job has W / njobs
+// waves of its own (W the grid's waves; when that is at least 1), each
+// decoding every (W / njobs)-th superblock of the job with the pipelined
+// single-stream decoder.
 template <bool WIDE, uint32_t OP>
 __global__ __launch_bounds__((WIDE ? WaveDec<double>::WAVES : WaveDec<float>::WAVES) * 64)
 __attribute__((amdgpu_waves_per_eu(WIDE ? 1 : 2, 2))) void k_batch_decode_w(
     const Job* __restrict__ jobs, const uint32_t* __restrict__ map, uint32_t njobs,
-    uint32_t total, Ctl C) {
+    uint32_t total, uint32_t uni, Ctl C) {
   constexpr uint32_t WAVES = WIDE ? WaveDec<double>::WAVES : WaveDec<float>::WAVES;
   constexpr uint32_t REGION = WIDE ? WaveDec<double>::REGION : WaveDec<float>::REGION;
   const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   uint32_t* R = g_stage + wid * REGION;
   bool bad = false;
   const uint32_t W = gridDim.x * WAVES;
+  if constexpr (!WIDE && OP == 1) {
+    const uint32_t wpj = njobs ? W / njobs : 0u;
+    if (uni && !map && wpj) {
+      const uint32_t w = blockIdx.x * WAVES + wid;
+      if (w < wpj * njobs) {
+        const Job J = jobs[w / wpj];
+        switch (uni) {
+          case 5: wave_job_decode<32>(J, w % wpj, wpj, R, bad); break;
+          case 6: wave_job_decode<64>(J, w % wpj, wpj, R, bad); break;
+          case 7: wave_job_decode<128>(J, w % wpj, wpj, R, bad); break;
+          default: bad = true; break;
+        }
+      }
+      if (bad && __lane_id() == 0) atomicOr(&C.ctrl->err, ERRF_CORRUPT);
+      return;
+    }
+  }
   for (uint32_t i = blockIdx.x * WAVES + wid; i < total; i += W) {
     const uint32_t j = map ? map[2 * (uint64_t)i] : i % njobs;
     const uint64_t sb = map ? map[2 * (uint64_t)i + 1] : i / njobs;
@@ -3242,23 +3285,24 @@ hipError_t launch_accum_wave(const Job& J, const Ctl& C, uint32_t cus, hipStream
 
 template <bool WIDE, uint32_t OP>
 static hipError_t launch_bdw(const Job* d_jobs, const uint32_t* d_map, uint32_t njobs,
-                             uint32_t total, uint32_t cus, const Ctl& C, hipStream_t st) {
+                             uint32_t total, uint32_t uni, uint32_t cus, const Ctl& C,
+                             hipStream_t st) {
   constexpr uint32_t WAVES = WIDE ? WaveDec<double>::WAVES : WaveDec<float>::WAVES;
   const size_t lds = (size_t)WAVES * (WIDE ? WaveDec<double>::REGION : WaveDec<float>::REGION) * 4;
   const uint64_t need = ((uint64_t)total + WAVES - 1) / WAVES;
   const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(cus, need));
   hipLaunchKernelGGL((k_batch_decode_w<WIDE, OP>), dim3(grid), dim3(WAVES * 64), lds, st, d_jobs,
-                     d_map, njobs, total, C);
+                     d_map, njobs, total, uni, C);
   return hipGetLastError();
 }
 
 hipError_t launch_decode_wave_batch(uint32_t op, const Job* d_jobs, const uint32_t* d_map,
-                                    uint32_t njobs, uint32_t total, bool wide, uint32_t cus,
-                                    const Ctl& C, hipStream_t st) {
+                                    uint32_t njobs, uint32_t total, bool wide, uint32_t uni,
+                                    uint32_t cus, const Ctl& C, hipStream_t st) {
   if (op == 1)
-    return wide ? launch_bdw<true, 1>(d_jobs, d_map, njobs, total, cus, C, st)
-                : launch_bdw<false, 1>(d_jobs, d_map, njobs, total, cus, C, st);
-  if (op == 3 && !wide) return launch_bdw<false, 3>(d_jobs, d_map, njobs, total, cus, C, st);
+    return wide ? launch_bdw<true, 1>(d_jobs, d_map, njobs, total, 0, cus, C, st)
+                : launch_bdw<false, 1>(d_jobs, d_map, njobs, total, uni, cus, C, st);
+  if (op == 3 && !wide) return launch_bdw<false, 3>(d_jobs, d_map, njobs, total, 0, cus, C, st);
   return hipErrorInvalidValue;
 }
 
