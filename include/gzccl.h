@@ -80,8 +80,9 @@ typedef struct gz_graph gz_graph;
  * decompression of either type (also batched and scatter), fp32 1D
  * compression, the fused step and decode-and-accumulate; GZ_EUNSUPPORTED
  * elsewhere.  With no shape given or tuned, decompression (single and
- * batched) and the fused step take them; compression, decode-and-accumulate
- * and scatter decompression take strips.  mode 0 = 1D blocks, 1 = 8x8 tiles (block_len 64,
+ * batched; scatter decompression of fp32 chunks) and the fused step take
+ * them; compression, decode-and-accumulate and fp64 scatter decompression
+ * take strips.  mode 0 = 1D blocks, 1 = 8x8 tiles (block_len 64,
  * nx = row length, multiple of 8, n a multiple of 8*nx); select (mode 1):
  * 0 = int8 MLP selector, 1 = exhaustive trial, 2 = always L1D. */
 typedef struct {

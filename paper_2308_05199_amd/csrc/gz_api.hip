@@ -112,7 +112,7 @@ struct gz_plan {
   bool wave = false;  // per-wave encoding kernels (total = njobs x rounds)
   bool wave_dec = false;  // per-wave decoding kernels (total = superblocks)
   bool has_map = false;   // wave_dec: d_map lists (job, superblock) pairs
-  uint32_t uni = 0;       // wave_dec: uniform_wave_decode of the jobs
+  uint32_t jw = 0;        // wave_dec: d_map holds jw per-wave job shares
   uint32_t log2L = 5;
 };
 
@@ -339,13 +339,40 @@ uint32_t uniform_jobs(const std::vector<Job>& jobs) {
   return (uint32_t)jobs.size();
 }
 
-// For a per-wave decoding batch without a map: log2 of the block length when
-// every job is an fp32 1D stream of that block length without a scatter
-// offset (each job then gets waves of its own), else 0.
-uint32_t uniform_wave_decode(const std::vector<Job>& jobs) {
+// Per-wave shares of an fp32 1D decoding batch of `total` superblocks:
+// (job, first superblock, stride) triples, each job given waves in
+// proportion to its superblocks (at least one) out of the waves the
+// per-wave decoder is launched with; empty where that does not apply
+// (accumulation, fp64, tiles, more jobs than waves), and the (job,
+// superblock) map is used instead.
+std::vector<uint32_t> wave_job_shares(const gz_ctx* c, gz_op op, const std::vector<Job>& jobs,
+                                      bool wide, uint64_t total) {
+  std::vector<uint32_t> m;
+  if (op != GZ_OP_DECOMPRESS || wide || jobs.empty() || total == 0) return m;
   for (const Job& J : jobs)
-    if (J.dtype != 0 || J.mode != 0 || J.in_off || J.log2L != jobs[0].log2L) return 0;
-  return jobs.empty() ? 0u : jobs[0].log2L;
+    if (J.dtype != 0 || J.mode != 0 || J.NS == 0) return m;
+  const uint64_t W = std::min<uint64_t>((uint64_t)c->cus, (total + 7) / 8) * 8;  // 8 waves/CU
+  if (jobs.size() > W) return m;
+  std::vector<uint64_t> cnt(jobs.size());
+  uint64_t sum = 0;
+  for (size_t j = 0; j < jobs.size(); ++j) {
+    cnt[j] = std::max<uint64_t>(1, W * jobs[j].NS / total);
+    sum += cnt[j];
+  }
+  while (sum > W) {  // the minimum of one wave per job may overshoot
+    auto it = std::max_element(cnt.begin(), cnt.end());
+    if (*it <= 1) return m;
+    --*it;
+    --sum;
+  }
+  m.reserve(3 * sum);
+  for (size_t j = 0; j < jobs.size(); ++j)
+    for (uint64_t i = 0; i < cnt[j]; ++i) {
+      m.push_back((uint32_t)j);
+      m.push_back((uint32_t)i);
+      m.push_back((uint32_t)cnt[j]);
+    }
+  return m;
 }
 
 // Builds the jobs of a request batch; fills the strip map.
@@ -866,7 +893,11 @@ gz_status gz_scatter_decompress(gz_ctx* c, const void* d_packed, uint64_t packed
       (dtype != GZ_F32 && dtype != GZ_F64) || !params_ok(p, L) || tile_mode(p) || nchunks == 0)
     return GZ_EINVAL;
   if (nchunks > c->max_jobs) return GZ_ENOSPC;
-  const bool want_wave = p && p->threads == WAVE_TPB && wave_fits(c, 1, dtype);
+  // waves when asked for, or by default for fp32 chunks where each chunk can
+  // have waves of its own (else strips)
+  const bool asked = p && p->threads == WAVE_TPB;
+  const bool dflt = (!p || (p->threads == 0 && p->grid == 0)) && dtype == GZ_F32;
+  const bool want_wave = (asked || dflt) && wave_fits(c, 1, dtype);
   gz_params q;  // the strips' shape when waves were asked for (geometry, fallback)
   const gz_params* ps = p;
   if (p && p->threads == WAVE_TPB) {
@@ -901,13 +932,18 @@ gz_status gz_scatter_decompress(gz_ctx* c, const void* d_packed, uint64_t packed
     std::vector<uint32_t> smap;
     const uint64_t total = wave_decode_map(jobs, smap);
     if (batch_decode_wave_ok(c, GZ_OP_DECOMPRESS, jobs, dtype == GZ_F64, total)) {
-      gz_status r = stage_upload(c, jobs, smap, st);
-      if (r != GZ_OK) return r;
-      return hip_status(gzk::launch_decode_wave_batch(
-          1, c->d_jobs, smap.empty() ? nullptr : c->d_map, nchunks, (uint32_t)total,
-          dtype == GZ_F64, 0u, (uint32_t)c->cus, c->ctl(), st));
+      const std::vector<uint32_t> jm =
+          wave_job_shares(c, GZ_OP_DECOMPRESS, jobs, dtype == GZ_F64, total);
+      if (asked || !jm.empty()) {
+        gz_status r = stage_upload(c, jobs, jm.empty() ? smap : jm, st);
+        if (r != GZ_OK) return r;
+        return hip_status(gzk::launch_decode_wave_batch(
+            1, c->d_jobs, (smap.empty() && jm.empty()) ? nullptr : c->d_map, nchunks,
+            (uint32_t)total, dtype == GZ_F64, (uint32_t)(jm.size() / 3), (uint32_t)c->cus,
+            c->ctl(), st));
+      }
     }
-    if (p && p->threads == WAVE_TPB) return GZ_EUNSUPPORTED;
+    if (asked) return GZ_EUNSUPPORTED;
   }
   if (!tpb_fits(c, dtype == GZ_F64, false, tpb)) return GZ_EUNSUPPORTED;
   std::vector<uint32_t> map;
@@ -937,11 +973,13 @@ gz_status gz_batch(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t nreq,
     std::vector<uint32_t> smap;
     const uint64_t total = wave_decode_map(jobs, smap);
     if (batch_decode_wave_ok(c, op, jobs, wide, total)) {
-      r = stage_upload(c, jobs, smap, st);
+      const std::vector<uint32_t> jm = wave_job_shares(c, op, jobs, wide, total);
+      r = stage_upload(c, jobs, jm.empty() ? smap : jm, st);
       if (r != GZ_OK) return r;
       return hip_status(gzk::launch_decode_wave_batch(
-          (uint32_t)op, c->d_jobs, smap.empty() ? nullptr : c->d_map, (uint32_t)jobs.size(),
-          (uint32_t)total, wide, uniform_wave_decode(jobs), (uint32_t)c->cus, c->ctl(), st));
+          (uint32_t)op, c->d_jobs, (smap.empty() && jm.empty()) ? nullptr : c->d_map,
+          (uint32_t)jobs.size(), (uint32_t)total, wide, (uint32_t)(jm.size() / 3),
+          (uint32_t)c->cus, c->ctl(), st));
     }
     if (p && p->threads == WAVE_TPB) return GZ_EUNSUPPORTED;
   }
@@ -975,12 +1013,18 @@ gz_status gz_plan_create(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t
   if (r != GZ_OK) return r;
   bool wave_dec = false;
   uint64_t dec_total = 0;
+  uint32_t jw = 0;
   if ((op == GZ_OP_DECOMPRESS || op == GZ_OP_ACCUMULATE) && batch_wave_wanted(c, op, p, wide)) {
     std::vector<uint32_t> smap;
     dec_total = wave_decode_map(jobs, smap);
     wave_dec = batch_decode_wave_ok(c, op, jobs, wide, dec_total);
-    if (wave_dec) map.swap(smap);
-    else if (p && p->threads == WAVE_TPB) return GZ_EUNSUPPORTED;
+    if (wave_dec) {
+      std::vector<uint32_t> jm = wave_job_shares(c, op, jobs, wide, dec_total);
+      jw = (uint32_t)(jm.size() / 3);
+      map.swap(jm.empty() ? smap : jm);
+    } else if (p && p->threads == WAVE_TPB) {
+      return GZ_EUNSUPPORTED;
+    }
   }
   const bool wave = !wave_dec && !wide && batch_wave_wanted(c, op, p) && batch_wave_ok(c, op, jobs);
   if (p && p->threads == WAVE_TPB && !wave && !wave_dec) return GZ_EUNSUPPORTED;
@@ -1019,7 +1063,7 @@ gz_status gz_plan_create(gz_ctx* c, gz_op op, const gz_request* h_reqs, uint32_t
   if (wave_dec) {
     pl->wave_dec = true;
     pl->has_map = !map.empty();
-    pl->uni = uniform_wave_decode(jobs);
+    pl->jw = jw;
     pl->njobs = (uint32_t)jobs.size();
     pl->total = (uint32_t)dec_total;
   }
@@ -1044,7 +1088,7 @@ gz_status gz_plan_launch(gz_plan* pl, gz_stream_t stream) {
   if (pl->wave_dec)
     return hip_status(gzk::launch_decode_wave_batch(
         pl->op, pl->d_jobs, pl->has_map ? pl->d_map : nullptr, pl->njobs, pl->total, pl->wide,
-        pl->uni, (uint32_t)pl->ctx->cus, pl->ctx->ctl(), (hipStream_t)stream));
+        pl->jw, (uint32_t)pl->ctx->cus, pl->ctx->ctl(), (hipStream_t)stream));
   return hip_status(gzk::launch_batch(pl->op, pl->d_jobs, pl->d_map, pl->njobs, pl->total,
                                       pl->ctx->ctl(),
                                       pl->tpb, pl->grid, pl->wide, (hipStream_t)stream));

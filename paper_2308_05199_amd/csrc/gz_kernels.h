@@ -27,12 +27,12 @@ hipError_t launch_accum_wave(const Job& J, const Ctl& C, uint32_t cus, hipStream
 // Per-wave batched decoding (op 1) or decode-and-accumulate (op 3, fp32):
 // total superblocks, superblock i = (d_map[2i], d_map[2i+1]) as (job,
 // superblock), or without a map (jobs of equal superblock counts) superblock
-// i / njobs of job i % njobs.  wide: the batch holds fp64 jobs.  uni (op 1,
-// no map): log2 of the block length if every job is an fp32 1D stream of
-// that block length without a scatter offset (jobs then get waves of their
-// own, each job's whole superblocks decoded as a pipeline), else 0.
+// i / njobs of job i % njobs.  wide: the batch holds fp64 jobs.  jw (op 1,
+// fp32 1D jobs): d_map holds jw (job, first superblock, stride) triples,
+// one per wave's share of a job (each job's whole superblocks decoded as a
+// pipeline); 0 otherwise.
 hipError_t launch_decode_wave_batch(uint32_t op, const Job* d_jobs, const uint32_t* d_map,
-                                    uint32_t njobs, uint32_t total, bool wide, uint32_t uni,
+                                    uint32_t njobs, uint32_t total, bool wide, uint32_t jw,
                                     uint32_t cus, const Ctl& C, hipStream_t st);
 // Per-wave fp32 1D encoding (op 0) or fused step (op 2): every wave encodes
 // whole superblocks, a workgroup's waves the 8 of a round (one chain

@@ -2154,12 +2154,11 @@ __device__ __forceinline__ bool wave_batch_super(const Job& J, uint64_t sb, uint
   return wave_decode_super<T, L, OP>(Jl, in, sb, paydw, t, R, raw, ~0ull);
 }
 
-// Superblocks first, first + stride, ... of one fp32 stream (job J, no
-// scatter offset) by one wave, whole ones pipelined as in k_decompress_w.
+// Superblocks first, first + stride, ... of one fp32 stream (job J, its
+// stream at in) by one wave, whole ones pipelined as in k_decompress_w.
 template <int L>
-__device__ __forceinline__ void wave_job_decode(const Job& J, uint64_t first, uint64_t stride,
-                                                uint32_t* R, bool& bad) {
-  const uint8_t* in = (const uint8_t*)J.in;
+__device__ __forceinline__ void wave_job_decode(const Job& J, const uint8_t* in, uint64_t first,
+                                                uint64_t stride, uint32_t* R, bool& bad) {
   uint64_t paydw = 0;
   float t = 0;
   if (!wave_header<float>(J, in, paydw, t)) {
@@ -2179,17 +2178,16 @@ __device__ __forceinline__ void wave_job_decode(const Job& J, uint64_t first, ui
 // superblock i is superblock map[2i + 1] of job map[2i], or, without a map
 // (jobs of equal superblock counts), superblock i / njobs of job i % njobs;
 // waves take them statically.  WIDE: the batch holds fp64 jobs (fp64-sized
-// regions, four waves per workgroup).  uni (decoding without a map): log2
-// of the block length when every job is an fp32 1D stream of that block
-// length without a scatter offset, else 0; then each job has W / njobs
-// waves of its own (W the grid's waves; when that is at least 1), each
-// decoding every (W / njobs)-th superblock of the job with the pipelined
-// single-stream decoder.
+// regions, four waves per workgroup).  jw (decoding an fp32 1D batch): the
+// map holds jw (job, first superblock, stride) triples instead, one per
+// wave's share (waves take them statically): each decodes superblocks
+// first, first + stride, ... of its job with the pipelined single-stream
+// decoder.
 template <bool WIDE, uint32_t OP>
 __global__ __launch_bounds__((WIDE ? WaveDec<double>::WAVES : WaveDec<float>::WAVES) * 64)
 __attribute__((amdgpu_waves_per_eu(WIDE ? 1 : 2, 2))) void k_batch_decode_w(
     const Job* __restrict__ jobs, const uint32_t* __restrict__ map, uint32_t njobs,
-    uint32_t total, uint32_t uni, Ctl C) {
+    uint32_t total, uint32_t jw, Ctl C) {
   constexpr uint32_t WAVES = WIDE ? WaveDec<double>::WAVES : WaveDec<float>::WAVES;
   constexpr uint32_t REGION = WIDE ? WaveDec<double>::REGION : WaveDec<float>::REGION;
   const uint32_t wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -2197,15 +2195,17 @@ __attribute__((amdgpu_waves_per_eu(WIDE ? 1 : 2, 2))) void k_batch_decode_w(
   bool bad = false;
   const uint32_t W = gridDim.x * WAVES;
   if constexpr (!WIDE && OP == 1) {
-    const uint32_t wpj = njobs ? W / njobs : 0u;
-    if (uni && !map && wpj) {
-      const uint32_t w = blockIdx.x * WAVES + wid;
-      if (w < wpj * njobs) {
-        const Job J = jobs[w / wpj];
-        switch (uni) {
-          case 5: wave_job_decode<32>(J, w % wpj, wpj, R, bad); break;
-          case 6: wave_job_decode<64>(J, w % wpj, wpj, R, bad); break;
-          case 7: wave_job_decode<128>(J, w % wpj, wpj, R, bad); break;
+    if (jw) {
+      for (uint32_t w = blockIdx.x * WAVES + wid; w < jw; w += W) {
+        Job J = jobs[map[3 * (uint64_t)w]];
+        const uint64_t first = map[3 * (uint64_t)w + 1], stride = map[3 * (uint64_t)w + 2];
+        const uint64_t off = J.in_off ? J.in_off[J.job] : 0ull;
+        J.in_bytes = off <= J.in_bytes ? J.in_bytes - off : 0ull;
+        const uint8_t* in = (const uint8_t*)J.in + off;
+        switch (J.log2L) {
+          case 5: wave_job_decode<32>(J, in, first, stride, R, bad); break;
+          case 6: wave_job_decode<64>(J, in, first, stride, R, bad); break;
+          case 7: wave_job_decode<128>(J, in, first, stride, R, bad); break;
           default: bad = true; break;
         }
       }
@@ -3285,23 +3285,23 @@ hipError_t launch_accum_wave(const Job& J, const Ctl& C, uint32_t cus, hipStream
 
 template <bool WIDE, uint32_t OP>
 static hipError_t launch_bdw(const Job* d_jobs, const uint32_t* d_map, uint32_t njobs,
-                             uint32_t total, uint32_t uni, uint32_t cus, const Ctl& C,
+                             uint32_t total, uint32_t jw, uint32_t cus, const Ctl& C,
                              hipStream_t st) {
   constexpr uint32_t WAVES = WIDE ? WaveDec<double>::WAVES : WaveDec<float>::WAVES;
   const size_t lds = (size_t)WAVES * (WIDE ? WaveDec<double>::REGION : WaveDec<float>::REGION) * 4;
-  const uint64_t need = ((uint64_t)total + WAVES - 1) / WAVES;
+  const uint64_t need = ((uint64_t)(jw ? jw : total) + WAVES - 1) / WAVES;
   const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(cus, need));
   hipLaunchKernelGGL((k_batch_decode_w<WIDE, OP>), dim3(grid), dim3(WAVES * 64), lds, st, d_jobs,
-                     d_map, njobs, total, uni, C);
+                     d_map, njobs, total, jw, C);
   return hipGetLastError();
 }
 
 hipError_t launch_decode_wave_batch(uint32_t op, const Job* d_jobs, const uint32_t* d_map,
-                                    uint32_t njobs, uint32_t total, bool wide, uint32_t uni,
+                                    uint32_t njobs, uint32_t total, bool wide, uint32_t jw,
                                     uint32_t cus, const Ctl& C, hipStream_t st) {
   if (op == 1)
     return wide ? launch_bdw<true, 1>(d_jobs, d_map, njobs, total, 0, cus, C, st)
-                : launch_bdw<false, 1>(d_jobs, d_map, njobs, total, uni, cus, C, st);
+                : launch_bdw<false, 1>(d_jobs, d_map, njobs, total, jw, cus, C, st);
   if (op == 3 && !wide) return launch_bdw<false, 3>(d_jobs, d_map, njobs, total, 0, cus, C, st);
   return hipErrorInvalidValue;
 }
