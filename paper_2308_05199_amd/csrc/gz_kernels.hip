@@ -1844,27 +1844,25 @@ __device__ __forceinline__ const uint32_t* wave_stage_payload(const uint32_t* sr
   return dst + delta;
 }
 
-// Decodes superblock sb into J.out (OP 1), or adds it to the fp32 values
-// there (OP 3, decode-and-accumulate); false (nothing written) if it is
-// malformed.  raw: sb's table and header-byte words (wave_blocks_load), on
-// return those of the wave's next superblock nsb (if it exists), whose
-// loads go out with this superblock's payload copy.
-// wave_stage_payload in two parts, so that a superblock's payload is in
-// flight while the wave decodes the previous one.  Issue: the first 512
-// chunks (8 per lane) and the partial last chunk's dwords into registers,
-// every load issued whatever the size (clamped to the readable bytes
-// [16-byte floor of src, src + P), or to the stream header's first aligned
-// chunk if that range is empty), so that each path issues the same memory
-// operations.  Commit: those into dst, and any chunks past the first 512
-// (payloads over 2048 dwords) copied there and then.
 // The stream header's first 16-byte aligned chunk (always readable once the
 // header has been checked).
 __device__ __forceinline__ const uint32_t* hdr_chunk(const uint8_t* in) {
   return (const uint32_t*)(in + ((0u - (uint32_t)(uintptr_t)in) & 15u));  // keeps in's address space
 }
 
+// wave_stage_payload in two parts, so that a superblock's payload is in
+// flight while the wave decodes the previous one.  Issue: the first
+// PAY_CPL * 64 chunks (PAY_CPL per lane: payloads up to 2048 dwords, ratio
+// 2 and up; 12 per lane measured no faster on ratio-1.7 data) and the
+// partial last chunk's dwords into registers, every
+// load issued whatever the size (clamped to the readable bytes [16-byte
+// floor of src, src + P), or to the stream header's first aligned chunk if
+// that range is empty), so that each path issues the same memory
+// operations.  Commit: those into dst, and any chunks past them copied
+// there and then.
+constexpr uint32_t PAY_CPL = 8;
 struct PayRegs {
-  u4u r[8];
+  u4u r[PAY_CPL];
   uint32_t t[3];
   const u4u* al;
   uint32_t delta, full, nch, P;
@@ -1882,7 +1880,7 @@ __device__ __forceinline__ void wave_pay_issue(const uint32_t* src, uint32_t P, 
   const u4u* base = pr.full ? pr.al : safe;
   const uint32_t last = pr.full ? pr.full - 1 : 0u;
 #pragma unroll
-  for (uint32_t u = 0; u < 8; ++u) pr.r[u] = base[min(u * 64 + lane, last)];
+  for (uint32_t u = 0; u < PAY_CPL; ++u) pr.r[u] = base[min(u * 64 + lane, last)];
   const uint32_t nd = pr.delta + P;  // readable dwords from al
   const uint32_t* b32 = nd ? (const uint32_t*)pr.al : (const uint32_t*)safe;
   const uint32_t lastd = nd ? nd - 1 : 0u;
@@ -1895,7 +1893,7 @@ __device__ __forceinline__ const uint32_t* wave_pay_commit(const PayRegs& pr, ui
   const uint32_t lane = __lane_id();
   u4u* d4 = (u4u*)dst;
 #pragma unroll
-  for (uint32_t u = 0; u < 8; ++u)
+  for (uint32_t u = 0; u < PAY_CPL; ++u)
     if (u * 64 + lane < pr.full) d4[u * 64 + lane] = pr.r[u];
   if (pr.full < pr.nch && lane == 0) {
     const uint32_t lim = pr.delta + pr.P - 4 * pr.full;  // 1..3 valid dwords
@@ -1906,7 +1904,7 @@ __device__ __forceinline__ const uint32_t* wave_pay_commit(const PayRegs& pr, ui
     r.w = 0u;
     d4[pr.full] = r;
   }
-  for (uint32_t k0 = 8 * 64; k0 < pr.full; k0 += 8 * 64) {
+  for (uint32_t k0 = PAY_CPL * 64; k0 < pr.full; k0 += 8 * 64) {
     u4u r[8];
 #pragma unroll
     for (uint32_t u = 0; u < 8; ++u) r[u] = pr.al[min(k0 + u * 64 + lane, pr.full - 1)];
@@ -1922,6 +1920,11 @@ __device__ __forceinline__ void wave_unpack_store(const Job& J, uint64_t sb, uin
                                                   uint32_t* R, const uint32_t* S,
                                                   const WaveBlocks& wb, const u4u (&old)[NOLD]);
 
+// Decodes superblock sb into J.out (OP 1), or adds it to the fp32 values
+// there (OP 3, decode-and-accumulate); false (nothing written) if it is
+// malformed.  raw: sb's table and header-byte words (wave_blocks_load), on
+// return those of the wave's next superblock nsb (if it exists), whose
+// loads go out with this superblock's payload copy.
 template <typename T, int L, uint32_t OP = 1>
 __device__ bool wave_decode_super(const Job& J, const uint8_t* in, uint64_t sb, uint64_t paydw,
                                   T t, uint32_t* R, uint32_t (&raw)[3], uint64_t nsb) {
