@@ -209,7 +209,7 @@ def test_fused_minus_zero_identity(ctx):
 
 
 @pytest.mark.parametrize("dt", [np.float32, np.float64])
-@pytest.mark.parametrize("tpb", [0, 64])   # strip (default) and per-wave decoding
+@pytest.mark.parametrize("tpb", [0, 64])   # default (fp32: per-wave job shares; fp64: strips), per-wave
 def test_scatter_matches_oracle(ctx, oracle, dt, tpb):
     import torch
     say("scatter", dt.__name__)
@@ -326,6 +326,60 @@ def test_plan_and_graph_replays(ctx, oracle, gz):
 
 
 CORRUPTIONS = ["magic", "n", "reserved_kind", "table", "payload_total", "truncated", "pad"]
+
+
+def test_job_share_batches_match_oracle(ctx, oracle, gz):
+    """fp32 decoding batches of uneven jobs (sizes from a ragged part of one
+    superblock to 40 superblocks, every block length): each job decoded by
+    waves of its own (default and threads 64), bitwise the oracle's; a
+    corrupt job sets GZ_ECORRUPT and the next batch is clean; more jobs than
+    the grid has waves fall back to the (job, superblock) list."""
+    import torch
+    say("job shares")
+    g = np.random.default_rng(60)
+    ns = [int(v) for v in g.integers(100, 40 * 4096, 37)] + [4096, 4097, 1]
+    Ls = [(32, 64, 128)[i % 3] for i in range(len(ns))]
+    xs = [synth.sinusoids(n, seed=61 + i) for i, n in enumerate(ns)]
+    streams = [oracle.compress(x, 1e-4, block_len=L) for x, L in zip(xs, Ls)]
+    wants = [oracle.decompress(s) for s in streams]
+    ins = [torch.from_numpy(s).cuda() for s in streams]
+    ys = [torch.empty(n, device="cuda") for n in ns]
+    items = [dict(**{"in": i}, out=y, n=n, in_bytes=i.numel(), dtype=gz.GZ_F32, block_len=L)
+             for i, y, n, L in zip(ins, ys, ns, Ls)]
+    arr = ctx.requests(items)
+    for tpb in (0, 64):
+        for y in ys:
+            y.fill_(-1.0)
+        ctx.batch(gz.GZ_OP_DECOMPRESS, arr, threads=tpb)
+        torch.cuda.synchronize()
+        for w, y in zip(wants, ys):
+            assert y.cpu().numpy().tobytes() == w.tobytes(), tpb
+    assert_ok(ctx)
+    # a corrupt table word (superblock 1's offset) in a job of several superblocks
+    k = next(i for i, n in enumerate(ns) if n > 3 * 4096)
+    bad = streams[k].copy()
+    bad[64 + 4 * 1:64 + 4 * 2] = np.frombuffer(np.uint32(0x7FFFFFF0).tobytes(), np.uint8)
+    ins[k] = torch.from_numpy(bad).cuda()
+    items[k] = dict(items[k], **{"in": ins[k]})
+    ctx.batch(gz.GZ_OP_DECOMPRESS, ctx.requests(items), threads=64)
+    torch.cuda.synchronize()
+    assert ctx.device_status() == gz.GZ_ECORRUPT
+    ctx.batch(gz.GZ_OP_DECOMPRESS, arr, threads=64)
+    torch.cuda.synchronize()
+    assert_ok(ctx)
+    # 2100 one-superblock jobs: more than the 2048 waves of the grid
+    ns2 = [1000 + (i % 7) * 400 for i in range(2100)]
+    xs2 = [synth.sinusoids(n, seed=700 + (i % 5)) for i, n in enumerate(ns2)]
+    st2 = [oracle.compress(x, 1e-4) for x in xs2]
+    in2 = [torch.from_numpy(s).cuda() for s in st2]
+    y2 = [torch.full((n,), -1.0, device="cuda") for n in ns2]
+    items2 = [dict(**{"in": i}, out=y, n=n, in_bytes=i.numel(), dtype=gz.GZ_F32)
+              for i, y, n in zip(in2, y2, ns2)]
+    ctx.batch(gz.GZ_OP_DECOMPRESS, ctx.requests(items2), threads=64)
+    torch.cuda.synchronize()
+    for s, y in zip(st2, y2):
+        assert y.cpu().numpy().tobytes() == oracle.decompress(s).tobytes()
+    assert_ok(ctx)
 
 
 def _corrupt(oracle, corrupt, n, seed):
