@@ -52,7 +52,7 @@ def parse():
 def traffic_from_profiles():
     """HBM bytes per fused launch from the committed rocprofv3 counter
     summary (None if absent or stale)."""
-    path = os.path.join(ROOT, "profiles", "fused_ring_config2_traffic.txt")
+    path = os.path.join(ROOT, "profiles", "fused_ring_8x256cube_traffic.txt")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -236,7 +236,7 @@ def extra_batch(ctx, gz, torch, nreq=4096):
 def extra_selector(ctx, gz, torch):
     """Learned predictor selection at full size: the int8 network is trained
     on the GPU on exhaustive-trial labels of seed-disjoint fields, then the
-    config-4 fields (546 M fp32 elements: 3D GRFs, noisy images, 50%-zero
+    the selector's mixed fields (546 M fp32 elements: 3D GRFs, noisy images, 50%-zero
     sparse; 8x8 tiles, eb 1e-4 x range) are compressed with the network,
     with exhaustive trial, with always-L1D tiles (the method without the
     network) and as 1D blocks.  Each mode's kernel time is the sum of its
@@ -267,7 +267,7 @@ def extra_selector(ctx, gz, torch):
             res[key][1] += t
     del test
     torch.cuda.empty_cache()
-    out = {"workload": "config-4 fields (10 GRFs 256^3, 40 images 2048^2, 50%-zero sparse "
+    out = {"workload": "mixed fields (10 GRFs 256^3, 40 images 2048^2, 50%-zero sparse "
                        "201 Mi; 546 M fp32), 8x8 tiles, eb 1e-4 x range; int8 MLP 16-32-3 "
                        "trained on the GPU on seed-disjoint fields",
            "elements": raw // 4, "train_s": train_s,
@@ -285,7 +285,7 @@ def extra_selector(ctx, gz, torch):
 
 def extra_sweep(gz, torch):
     """Fig. 3 analogue (Sec. 3.2.2, "GPU time stagnates for small inputs"):
-    compress throughput of one call of n elements (config-1 recipe, eb 1e-4)
+    compress throughput of one call of n elements (sum-of-sinusoids field, eb 1e-4)
     for n = 2^14 .. 2^28, and of 2^26 elements as 2^26/n requests of n
     elements in one persistent launch (a plan: one kernel launch)."""
     import numpy as np
@@ -327,7 +327,7 @@ def extra_sweep(gz, torch):
     ctx.close()
     del x
     torch.cuda.empty_cache()
-    return {"workload": "config-1 recipe, eb 1e-4, L 32: one call of n elements vs 2^26/n "
+    return {"workload": "sum-of-sinusoids field, eb 1e-4, L 32: one call of n elements vs 2^26/n "
                         "requests of n in one launch", "points": rows, "device_status": st}
 
 
@@ -496,7 +496,7 @@ def cpu_baseline(bufs_np, eb):
     t_one = run(False)
     threads = oracle.threads()
     return {"value": raw / t_all / 1e9, "unit": "GB/s", "cores": threads, "kind": "oracle",
-            "sample": "the full config-2 reduce-scatter (8 chunks x (1 compress + 7 fused "
+            "sample": "the full ring reduce-scatter of 8 x 256^3 ranks (8 chunks x (1 compress + 7 fused "
                       f"steps), 512 MiB of rank data), all-core variant (superblocks on "
                       f"{threads} threads, serial offset scan): {t_all:.1f} s",
             "single_core": {"value": raw / t_one / 1e9, "unit": "GB/s", "cores": 1,
@@ -507,7 +507,7 @@ def cpu_baseline(bufs_np, eb):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (this build simulates the ring's ranks inside "
+        print(f"bench.py measures one GPU only (the ring's ranks are simulated inside "
               f"one GPU's HBM); --gpus {args.gpus} is not supported.", file=sys.stderr)
         sys.exit(2)
     import numpy as np

@@ -19,7 +19,7 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 def test_profiles_name_their_command_and_kernel_source():
     """Each committed summary names the rocprofv3 command that made it and
     the SHA-256 of the kernel source it was taken with."""
-    for name in ("fused_ring_config2_traffic.txt", "ring_config2_kernel_trace.txt"):
+    for name in ("fused_ring_8x256cube_traffic.txt", "ring_reduce_scatter_8x256cube_kernel_trace.txt"):
         text = open(os.path.join(ROOT, "profiles", name)).read()
         assert re.search(r"[0-9a-f]{64}", text), name
         assert "rocprofv3" in text and "bench.py" in text
@@ -37,9 +37,9 @@ def test_traffic_is_reported_only_for_the_profiled_kernels(tmp_path, monkeypatch
     (tmp_path / "paper_2308_05199_amd" / "csrc").mkdir(parents=True)
     (tmp_path / "paper_2308_05199_amd" / "csrc" / "gz_kernels.hip").write_bytes(src)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    (prof / "fused_ring_config2_traffic.txt").write_text(
+    (prof / "fused_ring_8x256cube_traffic.txt").write_text(
         f"kernel_source_sha256 = {sha}\nhbm_bytes_per_launch = 123456\n")
     assert bench.traffic_from_profiles() == 123456.0
-    (prof / "fused_ring_config2_traffic.txt").write_text(
+    (prof / "fused_ring_8x256cube_traffic.txt").write_text(
         f"kernel_source_sha256 = {'0' * 64}\nhbm_bytes_per_launch = 123456\n")
     assert bench.traffic_from_profiles() is None

@@ -85,9 +85,9 @@ def test_compress_matches_oracle(ctx, oracle, dt, L, tpb):
     assert_ok(ctx)
 
 
-def test_compress_config1_full(ctx, oracle):
+def test_compress_sinusoid_field_2p20(ctx, oracle):
     """2^20-element sum of sinusoids + noise, eb 1e-4, L 32."""
-    say("config1 compress")
+    say("sinusoid field 2^20 compress")
     x = synth.sinusoids(1 << 20, seed=0)
     got = gpu_stream(ctx, x, 1e-4)
     want = oracle.compress(x, 1e-4)

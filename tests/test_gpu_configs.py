@@ -43,7 +43,7 @@ def ctx(gz):
     c.close()
 
 
-def test_ring_config2_full(gz, ctx, oracle):
+def test_ring_reduce_scatter_8x256cube_full(gz, ctx, oracle):
     """8 ranks x 256^3, 8 chunks of 2^21, 7 fused steps: every chunk's final
     stream equals the oracle's chain byte for byte, after an eager pass and
     after each of two graph replays; every chunk decodes bit for bit as the
@@ -51,7 +51,7 @@ def test_ring_config2_full(gz, ctx, oracle):
     sum."""
     import torch
     from paper_2308_05199_amd.ring import RingReduceScatter
-    say("ring config 2")
+    say("ring 8 x 256^3")
     bufs_np = synth.ring_ranks(8, (256, 256, 256), seed=0)
     eb = synth.relative_eb(bufs_np, 1e-4)
     bufs = [torch.from_numpy(b).cuda() for b in bufs_np]
@@ -98,14 +98,14 @@ def test_ring_config2_full(gz, ctx, oracle):
     assert ctx.device_status() == 0
 
 
-def test_scatter_config3_full(gz, ctx, oracle):
+def test_scatter_frames_64_chunks_full(gz, ctx, oracle):
     """1 GiB of 2048x2048 frames in 64 log-uniform chunks (1-64 MiB), one
     persistent compress launch and one batched decompress launch: every
     chunk's stream equals the oracle's byte for byte, offsets are the
     exclusive sum of sizes, and the batched decode equals the oracle's
     decode of every chunk bit for bit (so it is within eb everywhere)."""
     import torch
-    say("scatter config 3")
+    say("scatter 64 frames, 64 chunks")
     nfr = 64
     root = synth.frames(nfr, 2048, 2048, seed=0).reshape(-1)
     counts, displs = synth.loguniform_counts(root.size, 64, 1 << 18, 1 << 24, seed=1)
@@ -136,12 +136,12 @@ def test_scatter_config3_full(gz, ctx, oracle):
     assert ctx.device_status() == 0
 
 
-def test_batch_config5_shape(gz, ctx, oracle):
+def test_batch_4096_requests_shape(gz, ctx, oracle):
     """Mixed fp32/fp64 requests, log-uniform 4 KiB - 1 MiB, eb log-uniform
     in [1e-6, 1e-2], block lengths 32/64/128, one persistent launch each
     way; sampled requests against the oracle."""
     import torch
-    say("batch config 5")
+    say("batch 4096 requests")
     reqs = synth.mixed_requests(400, seed=5, lo_bytes=4096, hi_bytes=1 << 20)
     data = [synth.request_data(r) for r in reqs]
     ins, outs, nbs, items = [], [], [], []
@@ -202,8 +202,8 @@ def test_tuner_keeps_bytes(gz, ctx, oracle, tmp_path):
     assert out[:int(nb.item())].cpu().numpy().tobytes() == want.tobytes()
 
 
-def config5_inputs(gz, ctx_L=None):
-    """The config-5 requests generated on the device: 4096 requests,
+def mixed_4096_requests(gz, ctx_L=None):
+    """The 4096 mixed requests generated on the device: 4096 requests,
     log-uniform 4 KiB - 16 MiB, fp32/fp64, eb log-uniform in [1e-6, 1e-2],
     GRF-like (unit-variance random walk) or image-like (level + Poisson(50))
     rows.  Block lengths cycle 32/64/128, or are 0 (the context's tuned
@@ -241,7 +241,7 @@ def config5_inputs(gz, ctx_L=None):
 @pytest.mark.skip(reason="aborted once on the GPU inside torch.poisson (float64) while "
                          "generating its inputs, after the tuner calls had returned; no "
                          "cause found in this library, so the case stays off the GPU")
-def test_batch_config5_tuned_graph(gz, oracle, tmp_path):
+def test_batch_4096_requests_tuned_graph(gz, oracle, tmp_path):
     """Config 5 as the autotuner runs it: gz_tune picks each dtype's block
     length from {32, 64, 128} (requests give 0), gz_tune_batch the threads
     and grid of the batched compress and decompress launches; both run as
@@ -249,7 +249,7 @@ def test_batch_config5_tuned_graph(gz, oracle, tmp_path):
     every 128th request's bytes and decoded values equal the oracle's at
     the tuned length, after each replay."""
     import torch
-    say("batch config 5 tuned")
+    say("batch 4096 requests tuned")
     cache = str(tmp_path / "tune.jsonl")
     ctx = gz.Context(0, max_elems=(1 << 31), max_requests=4096)
     tf = ctx.tune(torch.from_numpy(synth.sinusoids(1 << 22, seed=9)).cuda(), 0, cache)
@@ -257,7 +257,7 @@ def test_batch_config5_tuned_graph(gz, oracle, tmp_path):
     Ls = {gz.GZ_F32: tf.block_len, gz.GZ_F64: td.block_len}
     say("tuned L", Ls, "threads", tf.threads, td.threads)
     assert set(Ls.values()) <= {32, 64, 128}
-    reqs, ins, outs, nbs, items = config5_inputs(gz, Ls)
+    reqs, ins, outs, nbs, items = mixed_4096_requests(gz, Ls)
     creq = ctx.requests(items)
     bc = ctx.tune_batch(gz.GZ_OP_COMPRESS, creq, cache)
     say("batch compress shape", bc.threads, bc.grid)
@@ -303,7 +303,7 @@ def test_batch_config5_tuned_graph(gz, oracle, tmp_path):
 
 
 def test_batch_tuned_graph(gz, oracle, tmp_path):
-    """The autotuned batch with the config-5 request mix (fp32/fp64,
+    """The autotuned batch with the 4096-request mix (fp32/fp64,
     log-uniform sizes, eb log-uniform in [1e-6, 1e-2], GRF-like and
     image-like rows) drawn on the host, 400 requests of 4 KiB - 2 MiB:
     gz_tune picks each dtype's block length from {32, 64, 128} (requests
@@ -374,15 +374,15 @@ def test_batch_tuned_graph(gz, oracle, tmp_path):
     ctx.close()
 
 
-def test_batch_config5_full(gz, oracle):
+def test_batch_4096_requests_full(gz, oracle):
     """The full batched workload: 4096 requests, log-uniform 4 KiB - 16 MiB
     (~8 GB), fp32/fp64, eb log-uniform in [1e-6, 1e-2], GRF-like or image-like
     rows generated on the device, block lengths 32/64/128; one persistent
     launch each way.  Every request decodes within its eb; every 128th
     request's bytes and decoded values equal the oracle's."""
     import torch
-    say("batch config 5 full")
-    reqs, ins, outs, nbs, items = config5_inputs(gz)
+    say("batch 4096 requests full")
+    reqs, ins, outs, nbs, items = mixed_4096_requests(gz)
     ctx = gz.Context(0, max_elems=sum(r["n"] for r in reqs) + 1, max_requests=4096)
     say("requests ready, bytes", sum(x.numel() * x.element_size() for x in ins))
     ctx.batch(gz.GZ_OP_COMPRESS, ctx.requests(items))

@@ -154,7 +154,7 @@ def test_adam_step_matches_formula(gz, ctx):
     assert np.allclose(W.cpu().numpy(), want, rtol=1e-5, atol=1e-6)
 
 
-def test_config4_full_size_sampled(gz, oracle):
+def test_selector_fields_full_size_sampled(gz, oracle):
     """512M fp32 elements of mixed fields (10 GRFs of 256^3 as 256-wide rows,
     40 noisy 2048^2 images, a 50%-zero sparse array as 8-wide rows) in tile
     mode with the int8 selector: windows of 64 rows of every kind of field
@@ -164,7 +164,7 @@ def test_config4_full_size_sampled(gz, oracle):
     import ctypes
     import torch
     from paper_2308_05199_amd import selector, synth
-    say("config 4 full size")
+    say("selector fields full size")
     ctx = gz.Context(0, max_elems=1 << 28, max_requests=64)
     blob = random_blob(11)
     selector.load(ctx, blob)
@@ -212,7 +212,7 @@ def test_trained_selector_against_exhaustive_trial(gz, oracle):
     """The learned part end to end: the network is trained on the GPU (the
     library's trial, gradient and Adam kernels) on labels from fields drawn
     with seeds disjoint from the test set's, exported to int8 and loaded.
-    On the config-4 fields (546 M elements) its compression ratio is within
+    On the mixed selector fields (546 M elements) its compression ratio is within
     3% of exhaustive trial and above both the method without the network
     (always-L1D tiles) and plain 1D blocks; its streams decode within eb, and
     sampled windows equal the oracle's with the trained weights."""
