@@ -351,7 +351,8 @@ std::vector<uint32_t> wave_job_shares(const gz_ctx* c, gz_op op, const std::vect
   if (op != GZ_OP_DECOMPRESS || wide || jobs.empty() || total == 0) return m;
   for (const Job& J : jobs)
     if (J.dtype != 0 || J.mode != 0 || J.NS == 0) return m;
-  const uint64_t W = std::min<uint64_t>((uint64_t)c->cus, (total + 7) / 8) * 8;  // 8 waves/CU
+  constexpr uint64_t WV = gzk::DEC_WAVES_F32;  // the launch: one workgroup per CU at most
+  const uint64_t W = std::min<uint64_t>((uint64_t)c->cus, (total + WV - 1) / WV) * WV;
   if (jobs.size() > W) return m;
   std::vector<uint64_t> cnt(jobs.size());
   uint64_t sum = 0;

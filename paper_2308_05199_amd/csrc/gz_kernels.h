@@ -45,6 +45,7 @@ hipError_t launch_encode_wave(uint32_t op, const Job* d_jobs, const Job& J, uint
                               hipStream_t st);
 size_t wave_encode_lds();  // its workgroup's LDS bytes
 constexpr uint64_t WAVE_ROUND = 8;  // superblocks per round of the per-wave encoder
+constexpr uint64_t DEC_WAVES_F32 = 8;  // waves per workgroup of the fp32 per-wave decoders
 inline uint64_t wave_rounds(uint64_t NS) { return (NS + WAVE_ROUND - 1) / WAVE_ROUND; }
 hipError_t launch_quantize(const void* x, uint64_t n, const Job& J, int32_t* q, uint8_t* fail,
                            hipStream_t st);

@@ -1639,6 +1639,7 @@ __device__ __forceinline__ void decompress_tp_one(const Job& J, uint64_t s, cons
 template <typename T>
 struct WaveDec {
   static constexpr uint32_t WAVES = sizeof(T) == 4 ? 8 : 4;               // per workgroup
+  static_assert(sizeof(T) != 4 || WAVES == DEC_WAVES_F32, "host's job shares assume this");
   static constexpr uint32_t REGION = 2 * 64 * seg_stride<T>() + 8;         // dwords per wave
 };
 
