@@ -2206,12 +2206,14 @@ __attribute__((amdgpu_waves_per_eu(WIDE ? 1 : 2, 2))) void k_batch_decode_w(
         const uint64_t off = J.in_off ? J.in_off[J.job] : 0ull;
         J.in_bytes = off <= J.in_bytes ? J.in_bytes - off : 0ull;
         const uint8_t* in = (const uint8_t*)J.in + off;
+        bool jb = false;  // this share's job only
         switch (J.log2L) {
-          case 5: wave_job_decode<32>(J, in, first, stride, R, bad); break;
-          case 6: wave_job_decode<64>(J, in, first, stride, R, bad); break;
-          case 7: wave_job_decode<128>(J, in, first, stride, R, bad); break;
-          default: bad = true; break;
+          case 5: wave_job_decode<32>(J, in, first, stride, R, jb); break;
+          case 6: wave_job_decode<64>(J, in, first, stride, R, jb); break;
+          case 7: wave_job_decode<128>(J, in, first, stride, R, jb); break;
+          default: jb = true; break;
         }
+        bad = bad || jb;
       }
       if (bad && __lane_id() == 0) atomicOr(&C.ctrl->err, ERRF_CORRUPT);
       return;
